@@ -1,0 +1,83 @@
+"""Pins of the oracle's learned-proposal decisions (refine around a proposal,
+fall back to full search).
+
+* a refine window that contains the full-search answer returns exactly it
+  (the key is a total order over the same candidates);
+* forcing every block to fall back reproduces full search;
+* decoding rounds half to even and clamps to the search radius;
+* the SAD threshold is floor(ratio * M * n) in double.
+"""
+import numpy as np
+
+
+def test_refine_around_exhaustive_answer_is_exact(oracle_mod):
+    from paper_2508_05990_amd import synth
+
+    f0, f1, _ = synth.small_pair(2)
+    B, R = 16, 8
+    mv_e, sad_e, _ = oracle_mod.full_search(f0, f1, B, R, nthreads=2)
+    rng = np.random.default_rng(0)
+    pred = (mv_e.astype(np.int32) + rng.integers(-2, 3, size=mv_e.shape)).clip(-R, R).astype(np.int16)
+    rp, cp = oracle_mod.pack_planes(f0), oracle_mod.pack_planes(f1)
+    mv_r, sad_r, _, _ = oracle_mod.stage_search(rp, cp, B, 2, 1, pred=pred, limit=R, nthreads=2)
+    assert np.array_equal(mv_r, mv_e) and np.array_equal(sad_r, sad_e)
+
+
+def test_forced_fallback_is_full_search(oracle_mod):
+    from paper_2508_05990_amd import synth
+
+    f0, f1, _ = synth.small_pair(4)
+    B, R = 16, 8
+    mv_e, sad_e, _ = oracle_mod.full_search(f0, f1, B, R, nthreads=2)
+    pred = np.zeros_like(mv_e)
+    logit = np.zeros(mv_e.shape[:2], np.float32)
+    mv, sad, fb = oracle_mod.proposal_search(f0, f1, B, R, pred, logit, np.inf, 1.5, 1.0)
+    assert fb.all() and np.array_equal(mv, mv_e) and np.array_equal(sad, sad_e)
+    # a SAD threshold of zero sends every block with a nonzero SAD back as well
+    mv, sad, fb = oracle_mod.proposal_search(f0, f1, B, R, pred, logit, -np.inf, 0.0, 1.0)
+    assert np.array_equal(fb.astype(bool), sad_e > 0) or fb.all()
+    assert np.array_equal(mv, mv_e) and np.array_equal(sad, sad_e)
+
+
+def test_confident_good_proposals_do_not_fall_back(oracle_mod):
+    from paper_2508_05990_amd import synth
+
+    f0, f1, _ = synth.small_pair(6)
+    B, R = 16, 8
+    mv_e, sad_e, _ = oracle_mod.full_search(f0, f1, B, R, nthreads=2)
+    logit = np.full(mv_e.shape[:2], 5.0, np.float32)
+    mv, sad, fb = oracle_mod.proposal_search(f0, f1, B, R, mv_e, logit, 0.0, 1e6, 1.0)
+    assert not fb.any()
+    assert np.array_equal(mv, mv_e) and np.array_equal(sad, sad_e)
+
+
+def test_out_of_frame_proposal_falls_back(oracle_mod):
+    """A proposal whose whole refine window lies outside the frame has no
+    candidate and must fall back."""
+    from paper_2508_05990_amd import synth
+
+    f0, f1, _ = synth.small_pair(7)
+    B, R = 16, 8
+    mv_e, _, _ = oracle_mod.full_search(f0, f1, B, R, nthreads=2)
+    pred = np.zeros_like(mv_e)
+    pred[0, 0] = (-8, -8)      # block (0,0): every candidate with dx<0 or dy<0 leaves the frame
+    logit = np.full(mv_e.shape[:2], 5.0, np.float32)
+    mv, _, fb = oracle_mod.proposal_search(f0, f1, B, R, pred, logit, 0.0, 1e6, 1.0)
+    assert fb[0, 0] == 1
+    assert tuple(mv[0, 0]) == tuple(mv_e[0, 0])
+
+
+def test_decode_rounds_half_even_and_clamps(oracle_mod):
+    o = np.array([[[0.0625, 0.1875, -0.0625, 100.0]], [[0.3125, -0.1875, 0.5, -100.0]]], np.float32)
+    p = oracle_mod.decode_proposal(o, 32)
+    # 8*o = 0.5 -> 0, 1.5 -> 2, -0.5 -> -0, 800 -> 32 ; 2.5 -> 2, -1.5 -> -2, 4 -> 4, -800 -> -32
+    assert p[0, :, 0].tolist() == [0, 2, 0, 32]
+    assert p[0, :, 1].tolist() == [2, -2, 4, -32]
+
+
+def test_sad_threshold(oracle_mod):
+    n = oracle_mod.block_samples(540, 960, 16)
+    assert n.shape == (34, 60) and n[0, 0] == 1024 and n[-1, 0] == 4 * 12 * 16
+    t = oracle_mod.sad_threshold(1.5, 2.0, n)
+    assert t[0, 0] == 3072 and t[-1, 0] == 2304
+    assert oracle_mod.sad_threshold(1.5, 1.1, 1000) == 1650
