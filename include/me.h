@@ -1,0 +1,180 @@
+/*
+ * me.h -- C ABI of the MI355X Bayer-domain motion-estimation library.
+ *
+ * The library computes, on one AMD Instinct MI355X (gfx950), the data-parallel
+ * hot path of "Efficient Bayer-Domain Video Computer Vision with Fast Motion
+ * Estimation and Learned Perception Residual" (arXiv 2508.05990):
+ *
+ *   MV     = ME(F_R, F_C)        block-matching motion estimation with the SAD
+ *                                criterion on raw Bayer frames (paper Sec. 2.2
+ *                                "Definition", Sec. 3.2 "Matching Criterion");
+ *   z_pred = Warp(z_R, MV)       propagation of the reference frame's feature
+ *                                map by the block vectors (paper Sec. 3.3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Pointers.  Every data pointer is a DEVICE pointer owned by the caller unless
+ *   the comment says "host".  The library never frees a caller pointer and
+ *   does not keep it past the stream work of the call.
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the null
+ *   stream).  Work is enqueued asynchronously; nothing is synchronised.
+ * Errors.  Arguments are validated before any device work, and a failed
+ *   validation enqueues nothing.  Launch failures return ME_E_HIP.  Faults of
+ *   the asynchronous work itself surface from the next synchronising HIP call.
+ *   me_last_error() gives a readable message for the calling thread's last
+ *   failure.  No C++ exception crosses this interface.
+ * Frames.  A frame is a Bayer mosaic of uint16 samples, RGGB at (0,0): R at
+ *   even row/even column, Gr at even/odd, Gb at odd/even, B at odd/odd.  The
+ *   search works on the four packed colour planes
+ *   P[c][y][x] = M[2y + (c>>1)][2x + (c&1)] (Hp = H/2 rows, Wp = W/2 columns),
+ *   read straight from the mosaic.  Sizes, radii and vectors are in packed
+ *   pixels (one packed pixel = two Bayer pixels in each direction).
+ * Blocks.  Block (i, j) covers packed rows [iB, min(iB+B, Hp)) and columns
+ *   [jB, min(jB+B, Wp)); the last row/column of blocks may be partial.
+ *   bh = ceil(Hp/B), bw = ceil(Wp/B).  Per-block outputs are row-major
+ *   [bh][bw].
+ * Vectors.  mv[b] = (dx, dy), int16, the position of the best match in the
+ *   reference frame minus the block's position in the current frame (a scene
+ *   translated by +s between reference and current gives -s).
+ * Selection.  Lowest SAD over the four planes (paper Sec. 3.2); ties go to the
+ *   smaller dx*dx+dy*dy, then the smaller dy, then the smaller dx, so the
+ *   result is unique.  Only candidates whose displaced block lies wholly
+ *   inside the reference frame are considered.
+ * Threads.  A context is not thread-safe; separate contexts are independent.
+ */
+#ifndef ME_H
+#define ME_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ME_OK = 0,
+    ME_E_INVAL = 1,        /* bad argument: null pointer, bad size, inconsistent geometry */
+    ME_E_UNSUPPORTED = 2,  /* valid request this build does not implement (e.g. B=12) */
+    ME_E_HIP = 3,          /* a HIP runtime call failed (no device, launch failure) */
+    ME_E_NOMEM = 4,        /* device or host allocation failed */
+    ME_E_STATE = 5         /* call not valid in the context's state (e.g. no weights loaded) */
+} me_status;
+
+typedef enum { ME_MODE_EXHAUSTIVE = 0, ME_MODE_PROPOSAL = 1 } me_mode;
+typedef enum { ME_F32 = 0, ME_BF16 = 1 } me_dtype;
+
+typedef struct me_ctx_s* me_ctx;
+
+/* A Bayer frame in device memory.  height and width (Bayer samples) are even
+ * and at least 2; pitch (elements between rows) is even and >= width; data is
+ * 4-byte aligned.  Samples are used as unsigned 16-bit values. */
+typedef struct {
+    const uint16_t* data;
+    int32_t height;
+    int32_t width;
+    int64_t pitch;
+} me_frame;
+
+typedef struct {
+    int32_t block;                 /* B, packed pixels: 8, 16, 32 or 64 */
+    int32_t radius;                /* R, candidates per side: 1..64 (full search: (2R+1)^2 candidates) */
+    int32_t step;                  /* candidate spacing; must be 1 in this build */
+    int32_t mode;                  /* me_mode */
+    int32_t refine_radius;         /* proposal mode: exact search radius around the proposal (0..8) */
+    float conf_logit_thresh;       /* proposal mode: fall back when logit < this (0 <=> confidence 0.5) */
+    float sad_ratio;               /* proposal mode: fall back when SAD > floor(ratio * M * n) */
+    float sad_median_per_sample;   /* proposal mode: M; <= 0 selects the value loaded with the weights */
+} me_params;
+
+/* Default parameters: B=16, R=32, step 1, exhaustive, refine radius 2,
+ * logit threshold 0, SAD ratio 1.5, median from the weights. */
+me_params me_default_params(void);
+
+/* Create a context on HIP device `device`.  Contexts own scratch buffers,
+ * loaded proposal weights and captured graphs.  *out is set on success. */
+me_status me_ctx_create(int32_t device, me_ctx* out);
+me_status me_ctx_destroy(me_ctx ctx);
+
+/*
+ * me_estimate -- MV = ME(F_R, F_C) (paper Sec. 2.2; Sec. 3.2 SAD criterion;
+ * full search of Sec. 2.2 in ME_MODE_EXHAUSTIVE).
+ *
+ * ref, cur : host structs describing device frames of equal height/width.
+ * params   : host struct; see me_params.
+ * mv       : device, int16 [bh][bw][2] (dx, dy), written.
+ * sad      : device, int32 [bh][bw], SAD of the chosen vector, written.
+ * fallback : device, uint8 [bh][bw] or NULL; in proposal mode 1 where the
+ *            block fell back to full search, 0 otherwise (all 0 in
+ *            exhaustive mode).
+ * ctx may be NULL in exhaustive mode (no state is needed); proposal mode
+ * needs a context with weights loaded (ME_E_STATE otherwise).
+ */
+me_status me_estimate(me_ctx ctx, const me_frame* ref, const me_frame* cur, const me_params* params,
+                      int16_t* mv, int32_t* sad, uint8_t* fallback, void* stream);
+
+/*
+ * me_stage_search -- one block-matching stage around per-block predictors
+ * (paper Sec. 3.2: one matching stage evaluates a set of candidates per
+ * block with one thread group per block).  Candidates are p + (u, v) with
+ * u, v in [-radius, radius]; a candidate is kept if the displaced block is
+ * inside the reference frame and |dx|, |dy| <= limit.
+ *
+ * pred : device int16 [bh][bw][2] (dx, dy), or NULL for p = 0.
+ * limit: 0..127.
+ * A block with no valid candidate gets sad = -1 and mv = (0, 0).
+ * ctx may be NULL.
+ */
+me_status me_stage_search(me_ctx ctx, const me_frame* ref, const me_frame* cur, int32_t block, int32_t radius,
+                          const int16_t* pred, int32_t limit, int16_t* mv, int32_t* sad, void* stream);
+
+/*
+ * me_warp_features -- z_pred = Warp(z_R, MV) (paper Sec. 3.3).
+ *
+ * z_ref : device [C][Hf][Wf], float32 or bfloat16 (dtype), contiguous.
+ * z_out : device, same type and shape, written; must not overlap z_ref.
+ * mv    : device int16 [bh][bw][2] from me_estimate with the same block size
+ *         on a frame of frame_h x frame_w Bayer samples.
+ * Geometry: s = (frame_h/2)/Hf must equal (frame_w/2)/Wf, be a whole number
+ * and divide `block` (ME_E_UNSUPPORTED otherwise).  Cell (i, j) lies in block
+ * (i*s/B, j*s/B); with that block's (dx, dy) the output is the bilinear
+ * sample of z_ref at (i + dy/s, j + dx/s), the two row and two column indices
+ * clamped into the map.  Float32 arithmetic; bfloat16 inputs are widened and
+ * the result is rounded to nearest even.
+ * ctx may be NULL.
+ */
+me_status me_warp_features(me_ctx ctx, const void* z_ref, void* z_out, int32_t dtype, int32_t C, int32_t Hf,
+                           int32_t Wf, const int16_t* mv, int32_t block, int32_t frame_h, int32_t frame_w,
+                           void* stream);
+
+/* One frame pair of a batch (me_batch_submit). */
+typedef struct {
+    me_frame ref;
+    me_frame cur;
+    me_params params;      /* exhaustive mode only */
+    int16_t* mv;           /* device [bh][bw][2] */
+    int32_t* sad;          /* device [bh][bw] */
+} me_job;
+
+/*
+ * me_batch_submit -- many independent frame pairs of mixed sizes, block sizes
+ * and radii in one launch (the paper's batched grid over (Batch, h, w),
+ * Sec. 4.1 CUDA settings, extended to uneven jobs).  jobs is a HOST array of
+ * n entries; results are bit-identical to n separate me_estimate calls.  The
+ * first submission of a given job-shape list captures a HIP graph in the
+ * context; later submissions with the same shapes replay it with the new
+ * pointers.  Needs a context.
+ */
+me_status me_batch_submit(me_ctx ctx, const me_job* jobs, int32_t n, void* stream);
+
+/* Human-readable name of a status code (static string). */
+const char* me_status_string(me_status s);
+
+/* Message describing the calling thread's last failed call (static per-thread
+ * buffer, valid until the thread's next failing call). */
+const char* me_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ME_H */

@@ -1,0 +1,259 @@
+// C ABI of the library (include/me.h): argument validation, launch planning
+// and dispatch to the HIP kernels.  Every check runs before the first HIP
+// call, so a rejected call enqueues nothing.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <new>
+#include <tuple>
+
+#include "../../include/me.h"
+#include "internal.h"
+
+using namespace me;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+me_status fail(me_status s, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+me_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(ME_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+me_status check_frame(const me_frame* f, const char* name)
+{
+    if (!f) return fail(ME_E_INVAL, "%s: null frame", name);
+    if (!f->data) return fail(ME_E_INVAL, "%s: null data pointer", name);
+    if (f->height < 2 || f->width < 2 || (f->height & 1) || (f->width & 1))
+        return fail(ME_E_INVAL, "%s: height and width must be even and >= 2 (got %d x %d)", name, f->height,
+                    f->width);
+    if (f->pitch < f->width || (f->pitch & 1))
+        return fail(ME_E_INVAL, "%s: pitch must be even and >= width (got %lld)", name, (long long)f->pitch);
+    if (reinterpret_cast<uintptr_t>(f->data) & 3u) return fail(ME_E_INVAL, "%s: data must be 4-byte aligned", name);
+    if (f->height > 65536 || f->width > 65536)
+        return fail(ME_E_UNSUPPORTED, "%s: frames above 65536 samples per side are not supported", name);
+    return ME_OK;
+}
+
+bool block_ok(int B) { return B == 8 || B == 16 || B == 32 || B == 64; }
+
+me_status check_pair(const me_frame* ref, const me_frame* cur)
+{
+    me_status s = check_frame(ref, "ref");
+    if (s != ME_OK) return s;
+    s = check_frame(cur, "cur");
+    if (s != ME_OK) return s;
+    if (ref->height != cur->height || ref->width != cur->width)
+        return fail(ME_E_INVAL, "ref and cur sizes differ (%dx%d vs %dx%d)", ref->height, ref->width, cur->height,
+                    cur->width);
+    return ME_OK;
+}
+
+SearchArgs make_args(const me_frame* ref, const me_frame* cur, int B, int R, int limit, const int16_t* pred,
+                     int16_t* mv, int32_t* sad)
+{
+    SearchArgs a{};
+    a.ref = reinterpret_cast<const uint32_t*>(ref->data);
+    a.cur = reinterpret_cast<const uint32_t*>(cur->data);
+    a.ref_pitch = ref->pitch / 2;
+    a.cur_pitch = cur->pitch / 2;
+    a.block = B;
+    a.Hp = cur->height / 2;
+    a.Wp = cur->width / 2;
+    a.bh = (a.Hp + B - 1) / B;
+    a.bw = (a.Wp + B - 1) / B;
+    a.R = R;
+    a.limit = limit;
+    a.pred = pred;
+    a.mv = mv;
+    a.sad = sad;
+    return a;
+}
+
+}  // namespace
+
+struct me_ctx_s {
+    int device = 0;
+    std::mutex mu;
+    // launch shapes picked by the tuner, keyed by (B, R, Hp, Wp)
+    std::map<std::tuple<int, int, int, int>, TileCfg> tuned;
+};
+
+namespace {
+
+TileCfg tiles_for(me_ctx ctx, int B, int R, int Hp, int Wp)
+{
+    if (ctx) {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        auto it = ctx->tuned.find(std::make_tuple(B, R, Hp, Wp));
+        if (it != ctx->tuned.end()) return it->second;
+    }
+    return default_tiles(B, R);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* me_status_string(me_status s)
+{
+    switch (s) {
+    case ME_OK: return "ME_OK";
+    case ME_E_INVAL: return "ME_E_INVAL";
+    case ME_E_UNSUPPORTED: return "ME_E_UNSUPPORTED";
+    case ME_E_HIP: return "ME_E_HIP";
+    case ME_E_NOMEM: return "ME_E_NOMEM";
+    case ME_E_STATE: return "ME_E_STATE";
+    }
+    return "ME_E_UNKNOWN";
+}
+
+const char* me_last_error(void) { return g_err; }
+
+me_params me_default_params(void)
+{
+    me_params p;
+    p.block = 16;
+    p.radius = 32;
+    p.step = 1;
+    p.mode = ME_MODE_EXHAUSTIVE;
+    p.refine_radius = 2;
+    p.conf_logit_thresh = 0.0f;
+    p.sad_ratio = 1.5f;
+    p.sad_median_per_sample = 0.0f;
+    return p;
+}
+
+me_status me_ctx_create(int32_t device, me_ctx* out)
+{
+    if (!out) return fail(ME_E_INVAL, "me_ctx_create: null output pointer");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= n) return fail(ME_E_INVAL, "me_ctx_create: device %d not in [0, %d)", device, n);
+    me_ctx c = new (std::nothrow) me_ctx_s;
+    if (!c) return fail(ME_E_NOMEM, "me_ctx_create: out of host memory");
+    c->device = device;
+    *out = c;
+    return ME_OK;
+}
+
+me_status me_ctx_destroy(me_ctx ctx)
+{
+    if (!ctx) return fail(ME_E_INVAL, "me_ctx_destroy: null context");
+    delete ctx;
+    return ME_OK;
+}
+
+me_status me_estimate(me_ctx ctx, const me_frame* ref, const me_frame* cur, const me_params* params, int16_t* mv,
+                      int32_t* sad, uint8_t* fallback, void* stream)
+{
+    me_status s = check_pair(ref, cur);
+    if (s != ME_OK) return s;
+    if (!params) return fail(ME_E_INVAL, "me_estimate: null params");
+    if (!mv || !sad) return fail(ME_E_INVAL, "me_estimate: null mv or sad");
+    const me_params& p = *params;
+    if (!block_ok(p.block)) return fail(ME_E_UNSUPPORTED, "me_estimate: block %d not in {8,16,32,64}", p.block);
+    if (p.radius < 0 || p.radius > 64) return fail(ME_E_INVAL, "me_estimate: radius %d not in [0,64]", p.radius);
+    if (p.step != 1) return fail(ME_E_UNSUPPORTED, "me_estimate: step %d (only 1 is supported)", p.step);
+    if (p.mode != ME_MODE_EXHAUSTIVE && p.mode != ME_MODE_PROPOSAL)
+        return fail(ME_E_INVAL, "me_estimate: unknown mode %d", p.mode);
+    if (p.mode == ME_MODE_PROPOSAL) return fail(ME_E_STATE, "me_estimate: proposal mode needs loaded weights");
+
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    SearchArgs a = make_args(ref, cur, p.block, p.radius, p.radius, nullptr, mv, sad);
+    const TileCfg cfg = tiles_for(ctx, p.block, p.radius, a.Hp, a.Wp);
+    hipError_t e = launch_sad_search(a, cfg, a.bh * a.bw, st);
+    if (e != hipSuccess) return hip_fail(e, "me_estimate: search launch");
+    if (fallback) {
+        e = launch_fill_u8(fallback, (size_t)a.bh * a.bw, 0, st);
+        if (e != hipSuccess) return hip_fail(e, "me_estimate: fallback fill");
+    }
+    return ME_OK;
+}
+
+me_status me_stage_search(me_ctx ctx, const me_frame* ref, const me_frame* cur, int32_t block, int32_t radius,
+                          const int16_t* pred, int32_t limit, int16_t* mv, int32_t* sad, void* stream)
+{
+    me_status s = check_pair(ref, cur);
+    if (s != ME_OK) return s;
+    if (!mv || !sad) return fail(ME_E_INVAL, "me_stage_search: null mv or sad");
+    if (!block_ok(block)) return fail(ME_E_UNSUPPORTED, "me_stage_search: block %d not in {8,16,32,64}", block);
+    if (radius < 0 || radius > 64) return fail(ME_E_INVAL, "me_stage_search: radius %d not in [0,64]", radius);
+    if (limit < 0 || limit > 127) return fail(ME_E_INVAL, "me_stage_search: limit %d not in [0,127]", limit);
+    SearchArgs a = make_args(ref, cur, block, radius, limit, pred, mv, sad);
+    const TileCfg cfg = tiles_for(ctx, block, radius, a.Hp, a.Wp);
+    hipError_t e = launch_sad_search(a, cfg, a.bh * a.bw, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "me_stage_search: launch");
+    return ME_OK;
+}
+
+me_status me_warp_features(me_ctx ctx, const void* z_ref, void* z_out, int32_t dtype, int32_t C, int32_t Hf,
+                           int32_t Wf, const int16_t* mv, int32_t block, int32_t frame_h, int32_t frame_w,
+                           void* stream)
+{
+    (void)ctx;
+    if (!z_ref || !z_out || !mv) return fail(ME_E_INVAL, "me_warp_features: null pointer");
+    if (dtype != ME_F32 && dtype != ME_BF16) return fail(ME_E_INVAL, "me_warp_features: unknown dtype %d", dtype);
+    if (C < 1 || Hf < 1 || Wf < 1) return fail(ME_E_INVAL, "me_warp_features: empty feature map");
+    if ((long long)C * Hf * Wf > (1LL << 40)) return fail(ME_E_UNSUPPORTED, "me_warp_features: map too large");
+    if ((long long)Hf * Wf > 0x7fffffffLL) return fail(ME_E_UNSUPPORTED, "me_warp_features: plane too large");
+    if (!block_ok(block)) return fail(ME_E_UNSUPPORTED, "me_warp_features: block %d not in {8,16,32,64}", block);
+    if (frame_h < 2 || frame_w < 2 || (frame_h & 1) || (frame_w & 1))
+        return fail(ME_E_INVAL, "me_warp_features: frame size must be even and >= 2");
+    const int Hp = frame_h / 2, Wp = frame_w / 2;
+    if (Hp % Hf || Wp % Wf || Hp / Hf != Wp / Wf)
+        return fail(ME_E_UNSUPPORTED, "me_warp_features: %dx%d map does not tile the %dx%d packed frame with square cells",
+                    Hf, Wf, Hp, Wp);
+    const int s = Hp / Hf;
+    if (block % s) return fail(ME_E_UNSUPPORTED, "me_warp_features: cell size %d does not divide block %d", s, block);
+    const size_t esz = dtype == ME_F32 ? 4 : 2;
+    const char* a0 = static_cast<const char*>(z_ref);
+    const char* b0 = static_cast<const char*>(z_out);
+    const size_t bytes = (size_t)C * Hf * Wf * esz;
+    if (a0 < b0 + bytes && b0 < a0 + bytes) return fail(ME_E_INVAL, "me_warp_features: z_out overlaps z_ref");
+    if ((reinterpret_cast<uintptr_t>(mv) & 3u)) return fail(ME_E_INVAL, "me_warp_features: mv must be 4-byte aligned");
+    const int bw = (Wp + block - 1) / block;
+    hipError_t e = launch_warp(z_ref, z_out, dtype == ME_BF16, C, Hf, Wf, mv, bw, block / s, s,
+                               reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "me_warp_features: launch");
+    return ME_OK;
+}
+
+me_status me_batch_submit(me_ctx ctx, const me_job* jobs, int32_t n, void* stream)
+{
+    if (!ctx) return fail(ME_E_INVAL, "me_batch_submit: null context");
+    if (n < 0 || (n > 0 && !jobs)) return fail(ME_E_INVAL, "me_batch_submit: bad job array");
+    for (int32_t k = 0; k < n; ++k) {
+        const me_job& j = jobs[k];
+        me_status s = check_pair(&j.ref, &j.cur);
+        if (s != ME_OK) return s;
+        if (!j.mv || !j.sad) return fail(ME_E_INVAL, "me_batch_submit: job %d: null mv or sad", k);
+        if (!block_ok(j.params.block)) return fail(ME_E_UNSUPPORTED, "me_batch_submit: job %d: bad block", k);
+        if (j.params.radius < 0 || j.params.radius > 64) return fail(ME_E_INVAL, "me_batch_submit: job %d: bad radius", k);
+        if (j.params.step != 1 || j.params.mode != ME_MODE_EXHAUSTIVE)
+            return fail(ME_E_UNSUPPORTED, "me_batch_submit: job %d: only exhaustive step-1 jobs", k);
+    }
+    for (int32_t k = 0; k < n; ++k) {
+        const me_job& j = jobs[k];
+        me_status s = me_estimate(ctx, &j.ref, &j.cur, &j.params, j.mv, j.sad, nullptr, stream);
+        if (s != ME_OK) return s;
+    }
+    return ME_OK;
+}
+
+}  // extern "C"

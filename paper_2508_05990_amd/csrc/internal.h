@@ -1,0 +1,65 @@
+// Internal declarations shared by the HIP sources of the library (not part of
+// the public ABI, which is include/me.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace me {
+
+// One block-matching stage over one frame pair.  Frames are read as 32-bit
+// words: word k of mosaic row r holds samples (r, 2k) and (r, 2k+1), i.e. the
+// packed-plane pixel column k of the two planes that live on row r's parity.
+// A packed displacement (dx, dy) is then a displacement of dx words and 2*dy
+// mosaic rows.
+struct SearchArgs {
+    const uint32_t* ref;
+    const uint32_t* cur;
+    int64_t ref_pitch;      // words per mosaic row
+    int64_t cur_pitch;
+    int32_t block;          // B, packed pixels (8, 16, 32, 64)
+    int32_t Hp, Wp;         // packed plane size
+    int32_t bh, bw;         // block grid
+    int32_t R;              // candidates per side around the predictor
+    int32_t limit;          // |dx|, |dy| <= limit
+    const int16_t* pred;    // [bh][bw][2] or null (predictor 0)
+    const int32_t* list;    // optional block list (device); null = all blocks
+    const int32_t* list_n;  // device count for `list` (blocks past it exit)
+    int16_t* mv;            // [bh][bw][2]
+    int32_t* sad;           // [bh][bw]
+    int32_t band_ty;        // candidate tile rows per LDS band
+    int32_t lds_pitch;      // words per LDS window row (multiple of 4)
+    int32_t col0, ncols;    // block columns covered by a launch without a list
+};
+
+// Launch shape of the search kernel.
+struct TileCfg {
+    int kx;        // horizontally adjacent candidates per lane
+    int ky;        // vertically adjacent candidates per lane
+    int nw;        // waves per workgroup
+    int band_ty;   // tile rows per LDS band
+    int lds_pitch; // words per LDS row
+    size_t lds_bytes;
+};
+
+// Fill in the LDS geometry of `cfg` (kx, ky, nw set) for block size B and a
+// candidate window of at most nx_max x ny_max; band_ty is the largest that
+// keeps the window within lds_cap bytes.  Returns false if no band fits.
+bool plan_tiles(int B, int nx_max, int ny_max, size_t lds_cap, TileCfg* cfg);
+
+// Default launch shape for block size B and radius R.
+TileCfg default_tiles(int B, int R);
+
+// Whether the kernel table has an instance for (B, kx, ky).
+bool tiles_supported(int B, int kx, int ky);
+
+hipError_t launch_sad_search(const SearchArgs& a, const TileCfg& cfg, int n_wg, hipStream_t stream);
+
+// Bilinear propagation of a feature map by block vectors.
+hipError_t launch_warp(const void* z, void* out, int bf16, int C, int Hf, int Wf, const int16_t* mv, int bw,
+                       int cells, int s, hipStream_t stream);
+
+hipError_t launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t stream);
+hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t stream);
+
+}  // namespace me

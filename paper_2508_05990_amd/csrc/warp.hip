@@ -1,0 +1,105 @@
+// Propagation of a reference feature map by per-block motion vectors,
+// z_pred = Warp(z_R, MV) (paper Sec. 3.3), on gfx950.
+//
+// HBM-bound: every output element reads four neighbouring inputs (mostly
+// L2/L1 hits, since neighbouring cells of a block share one vector) and is
+// written once.  A thread owns one cell (i, j) and a run of channels: the
+// vector, the two clamped row and column indices and the four bilinear
+// weights are computed once and reused for every channel; consecutive lanes
+// take consecutive cells of a row, so loads and stores of a channel plane are
+// contiguous across the wave.
+#include "internal.h"
+
+namespace me {
+namespace {
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t v) { return __uint_as_float((uint32_t)v << 16); }
+
+// Round to nearest, ties to even; NaN stays a quiet NaN.
+__device__ __forceinline__ uint16_t f32_to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ int floor_div(int a, int b)
+{
+    const int q = a / b;
+    return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+
+template <bool BF16>
+__global__ __launch_bounds__(256) void warp_kernel(const void* __restrict__ zin, void* __restrict__ zout, int C,
+                                                   int Hf, int Wf, const int16_t* __restrict__ mv, int bw, int cells,
+                                                   int s, float inv_s, int cpt)
+{
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ncell = Hf * Wf;
+    if (cell >= ncell) return;
+    const int i = cell / Wf, j = cell - i * Wf;
+    const int c0 = blockIdx.y * cpt;
+    const int c1 = min(C, c0 + cpt);
+
+    const int b = (i / cells) * bw + (j / cells);
+    const int32_t vec = reinterpret_cast<const int32_t*>(mv)[b];   // (dx, dy) as two int16
+    const int dx = (int16_t)(vec & 0xffff), dy = (int16_t)((uint32_t)vec >> 16);
+    const int ny = i * s + dy, nx = j * s + dx;
+    const int y0 = floor_div(ny, s), x0 = floor_div(nx, s);
+    const float wy = (float)(ny - y0 * s) * inv_s;
+    const float wx = (float)(nx - x0 * s) * inv_s;
+    const int ya = min(max(y0, 0), Hf - 1), yb = min(max(y0 + 1, 0), Hf - 1);
+    const int xa = min(max(x0, 0), Wf - 1), xb = min(max(x0 + 1, 0), Wf - 1);
+    const float w00 = (1.f - wy) * (1.f - wx), w01 = (1.f - wy) * wx;
+    const float w10 = wy * (1.f - wx), w11 = wy * wx;
+    const int o00 = ya * Wf + xa, o01 = ya * Wf + xb, o10 = yb * Wf + xa, o11 = yb * Wf + xb;
+
+    const size_t plane = (size_t)ncell;
+    for (int c = c0; c < c1; ++c) {
+        const size_t base = (size_t)c * plane;
+        float v00, v01, v10, v11;
+        if (BF16) {
+            const uint16_t* p = reinterpret_cast<const uint16_t*>(zin) + base;
+            v00 = bf16_to_f32(p[o00]);
+            v01 = bf16_to_f32(p[o01]);
+            v10 = bf16_to_f32(p[o10]);
+            v11 = bf16_to_f32(p[o11]);
+        } else {
+            const float* p = reinterpret_cast<const float*>(zin) + base;
+            v00 = p[o00];
+            v01 = p[o01];
+            v10 = p[o10];
+            v11 = p[o11];
+        }
+        float acc = w00 * v00;
+        acc = fmaf(w01, v01, acc);
+        acc = fmaf(w10, v10, acc);
+        acc = fmaf(w11, v11, acc);
+        if (BF16)
+            reinterpret_cast<uint16_t*>(zout)[base + cell] = f32_to_bf16(acc);
+        else
+            reinterpret_cast<float*>(zout)[base + cell] = acc;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_warp(const void* z, void* out, int bf16, int C, int Hf, int Wf, const int16_t* mv, int bw,
+                       int cells, int s, hipStream_t stream)
+{
+    const int ncell = Hf * Wf;
+    const int threads = 256;
+    const int cpt = C < 16 ? C : 16;
+    dim3 grid((ncell + threads - 1) / threads, (C + cpt - 1) / cpt);
+    const float inv_s = 1.0f / (float)s;
+    if (bf16)
+        hipLaunchKernelGGL(warp_kernel<true>, grid, dim3(threads), 0, stream, z, out, C, Hf, Wf, mv, bw, cells, s,
+                           inv_s, cpt);
+    else
+        hipLaunchKernelGGL(warp_kernel<false>, grid, dim3(threads), 0, stream, z, out, C, Hf, Wf, mv, bw, cells, s,
+                           inv_s, cpt);
+    return hipGetLastError();
+}
+
+}  // namespace me

@@ -1,0 +1,203 @@
+"""ctypes binding of the HIP library (include/me.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  PyTorch supplies device memory and streams.  Importing this module
+raises if the library has not been built -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libme.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("HIP library not built: %s (run paper_2508_05990_amd/build.py or __graft_entry__.build())"
+                      % LIB_PATH)
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+ME_OK, ME_E_INVAL, ME_E_UNSUPPORTED, ME_E_HIP, ME_E_NOMEM, ME_E_STATE = range(6)
+ME_MODE_EXHAUSTIVE, ME_MODE_PROPOSAL = 0, 1
+ME_F32, ME_BF16 = 0, 1
+
+
+class MeFrame(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("height", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("pitch", ctypes.c_int64)]
+
+
+class MeParams(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("radius", ctypes.c_int32), ("step", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("refine_radius", ctypes.c_int32),
+                ("conf_logit_thresh", ctypes.c_float), ("sad_ratio", ctypes.c_float),
+                ("sad_median_per_sample", ctypes.c_float)]
+
+
+class MeJob(ctypes.Structure):
+    _fields_ = [("ref", MeFrame), ("cur", MeFrame), ("params", MeParams), ("mv", ctypes.c_void_p),
+                ("sad", ctypes.c_void_p)]
+
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+
+
+def _sig(name, args, res=_I32):
+    f = getattr(_lib, name)
+    f.argtypes = args
+    f.restype = res
+    return f
+
+
+_me_default_params = _sig("me_default_params", [], MeParams)
+_me_ctx_create = _sig("me_ctx_create", [_I32, ctypes.POINTER(_P)])
+_me_ctx_destroy = _sig("me_ctx_destroy", [_P])
+_me_estimate = _sig("me_estimate", [_P, ctypes.POINTER(MeFrame), ctypes.POINTER(MeFrame), ctypes.POINTER(MeParams),
+                                    _P, _P, _P, _P])
+_me_stage_search = _sig("me_stage_search", [_P, ctypes.POINTER(MeFrame), ctypes.POINTER(MeFrame), _I32, _I32, _P,
+                                            _I32, _P, _P, _P])
+_me_warp_features = _sig("me_warp_features", [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _I32, _I32, _I32, _P])
+_me_batch_submit = _sig("me_batch_submit", [_P, ctypes.POINTER(MeJob), _I32, _P])
+_me_status_string = _sig("me_status_string", [_I32], ctypes.c_char_p)
+_me_last_error = _sig("me_last_error", [], ctypes.c_char_p)
+
+EXPORTS = ["me_default_params", "me_ctx_create", "me_ctx_destroy", "me_estimate", "me_stage_search",
+           "me_warp_features", "me_batch_submit", "me_status_string", "me_last_error"]
+
+
+class MeError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (_me_status_string(status).decode(), msg))
+        self.status = status
+
+
+def _check(status):
+    if status != ME_OK:
+        raise MeError(status, _me_last_error().decode())
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def frame_of(t: torch.Tensor) -> MeFrame:
+    """Describe a 2-D uint16/int16 device tensor (Bayer mosaic) as an me_frame."""
+    if t.dim() != 2 or t.element_size() != 2:
+        raise ValueError("a frame is a 2-D tensor of 16-bit samples")
+    if t.stride(1) != 1:
+        raise ValueError("frame rows must be contiguous")
+    return MeFrame(t.data_ptr(), t.shape[0], t.shape[1], t.stride(0))
+
+
+def block_grid(H, W, block):
+    return (H // 2 + block - 1) // block, (W // 2 + block - 1) // block
+
+
+def default_params() -> MeParams:
+    return _me_default_params()
+
+
+def make_params(block=16, radius=32, mode=ME_MODE_EXHAUSTIVE, refine_radius=2, conf_logit_thresh=0.0,
+                sad_ratio=1.5, sad_median_per_sample=0.0) -> MeParams:
+    p = default_params()
+    p.block, p.radius, p.step, p.mode = block, radius, 1, mode
+    p.refine_radius = refine_radius
+    p.conf_logit_thresh = conf_logit_thresh
+    p.sad_ratio = sad_ratio
+    p.sad_median_per_sample = sad_median_per_sample
+    return p
+
+
+class Context:
+    """Owner of an me_ctx (scratch buffers, tuned launch shapes, weights, graphs)."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(_me_ctx_create(device, ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            _check(_me_ctx_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ctx_handle(ctx):
+    return None if ctx is None else ctx.handle
+
+
+def estimate(ref: torch.Tensor, cur: torch.Tensor, block: int = 16, radius: int = 32, mv=None, sad=None,
+             fallback=None, params: MeParams | None = None, ctx: Context | None = None, stream=None):
+    """MV = ME(F_R, F_C) on two device Bayer mosaics; returns (mv [bh,bw,2] int16, sad [bh,bw] int32)."""
+    H, W = cur.shape
+    if params is None:
+        params = make_params(block, radius)
+    bh, bw = block_grid(H, W, params.block)
+    if mv is None:
+        mv = torch.empty((bh, bw, 2), dtype=torch.int16, device=cur.device)
+    if sad is None:
+        sad = torch.empty((bh, bw), dtype=torch.int32, device=cur.device)
+    fr, fc = frame_of(ref), frame_of(cur)
+    _check(_me_estimate(_ctx_handle(ctx), ctypes.byref(fr), ctypes.byref(fc), ctypes.byref(params), mv.data_ptr(),
+                        sad.data_ptr(), None if fallback is None else fallback.data_ptr(), _stream_handle(stream)))
+    return mv, sad
+
+
+def stage_search(ref, cur, block, radius, pred=None, limit=None, mv=None, sad=None, ctx=None, stream=None):
+    """One matching stage around per-block predictors (exhaustive when pred is None)."""
+    H, W = cur.shape
+    bh, bw = block_grid(H, W, block)
+    if limit is None:
+        limit = radius
+    if mv is None:
+        mv = torch.empty((bh, bw, 2), dtype=torch.int16, device=cur.device)
+    if sad is None:
+        sad = torch.empty((bh, bw), dtype=torch.int32, device=cur.device)
+    fr, fc = frame_of(ref), frame_of(cur)
+    _check(_me_stage_search(_ctx_handle(ctx), ctypes.byref(fr), ctypes.byref(fc), block, radius,
+                            None if pred is None else pred.data_ptr(), limit, mv.data_ptr(), sad.data_ptr(),
+                            _stream_handle(stream)))
+    return mv, sad
+
+
+def warp_features(z_ref: torch.Tensor, mv: torch.Tensor, block: int, frame_h: int, frame_w: int, out=None,
+                  ctx=None, stream=None):
+    """z_pred = Warp(z_R, MV); z_ref is [C, Hf, Wf] float32 or bfloat16 on the device."""
+    if z_ref.dtype == torch.float32:
+        dt = ME_F32
+    elif z_ref.dtype == torch.bfloat16:
+        dt = ME_BF16
+    else:
+        raise ValueError("features must be float32 or bfloat16")
+    if not z_ref.is_contiguous():
+        raise ValueError("features must be contiguous")
+    C, Hf, Wf = z_ref.shape
+    if out is None:
+        out = torch.empty_like(z_ref)
+    _check(_me_warp_features(_ctx_handle(ctx), z_ref.data_ptr(), out.data_ptr(), dt, C, Hf, Wf, mv.data_ptr(), block,
+                             frame_h, frame_w, _stream_handle(stream)))
+    return out
+
+
+def batch_submit(ctx: Context, jobs, stream=None):
+    """jobs: list of (ref, cur, block, radius, mv, sad) device tensors; one submission."""
+    arr = (MeJob * len(jobs))()
+    for k, (ref, cur, block, radius, mv, sad) in enumerate(jobs):
+        arr[k].ref = frame_of(ref)
+        arr[k].cur = frame_of(cur)
+        arr[k].params = make_params(block, radius)
+        arr[k].mv = mv.data_ptr()
+        arr[k].sad = sad.data_ptr()
+    _check(_me_batch_submit(ctx.handle, arr, len(jobs), _stream_handle(stream)))

@@ -1,0 +1,158 @@
+"""The C ABI library loads, exports every entry point include/me.h declares,
+and rejects bad arguments before any device work (runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "me.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(me_[a-z_0-9]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def me():
+    from paper_2508_05990_amd import me as mod
+
+    return mod
+
+
+def test_header_declares_core_calls():
+    names = _declared()
+    for n in ["me_estimate", "me_warp_features", "me_batch_submit", "me_stage_search", "me_ctx_create"]:
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(me):
+    lib = ctypes.CDLL(me.LIB_PATH)
+    for n in _declared():
+        assert hasattr(lib, n), n
+    assert set(me.EXPORTS) <= set(_declared())
+
+
+def test_status_strings(me):
+    assert me._me_status_string(0) == b"ME_OK"
+    assert me._me_status_string(2) == b"ME_E_UNSUPPORTED"
+
+
+def test_default_params(me):
+    p = me.default_params()
+    assert (p.block, p.radius, p.step, p.mode, p.refine_radius) == (16, 32, 1, 0, 2)
+    assert p.sad_ratio == pytest.approx(1.5)
+
+
+# Fake but non-null, 4-byte aligned "device" addresses: every case below must
+# be rejected by validation, so nothing is ever dereferenced or launched.
+FAKE = 0x10000
+
+
+def _frame(me, h=64, w=64, pitch=None, data=FAKE):
+    return me.MeFrame(data, h, w, w if pitch is None else pitch)
+
+
+def _est(me, ref, cur, params, mv=FAKE, sad=FAKE):
+    return me._me_estimate(None, ctypes.byref(ref), ctypes.byref(cur), ctypes.byref(params), mv, sad, None, None)
+
+
+@pytest.mark.parametrize("case,status", [
+    ("null_data", 1), ("odd_height", 1), ("odd_width", 1), ("tiny", 1), ("pitch_small", 1), ("pitch_odd", 1),
+    ("misaligned", 1), ("size_mismatch", 1), ("bad_block", 2), ("radius_big", 1), ("radius_neg", 1),
+    ("step2", 2), ("bad_mode", 1), ("null_mv", 1), ("proposal_no_ctx", 5), ("huge", 2),
+])
+def test_estimate_validation(me, case, status):
+    ref, cur = _frame(me), _frame(me)
+    p = me.make_params(16, 8)
+    mv, sad = FAKE, FAKE
+    if case == "null_data":
+        cur = _frame(me, data=0)
+    elif case == "odd_height":
+        cur = _frame(me, h=63)
+        ref = _frame(me, h=63)
+    elif case == "odd_width":
+        cur = _frame(me, w=63, pitch=64)
+    elif case == "tiny":
+        cur = _frame(me, h=0)
+    elif case == "pitch_small":
+        cur = _frame(me, pitch=32)
+    elif case == "pitch_odd":
+        cur = _frame(me, pitch=65)
+    elif case == "misaligned":
+        cur = _frame(me, data=FAKE + 2)
+    elif case == "size_mismatch":
+        cur = _frame(me, h=32)
+    elif case == "bad_block":
+        p.block = 12
+    elif case == "radius_big":
+        p.radius = 65
+    elif case == "radius_neg":
+        p.radius = -1
+    elif case == "step2":
+        p.step = 2
+    elif case == "bad_mode":
+        p.mode = 7
+    elif case == "null_mv":
+        mv = 0
+    elif case == "proposal_no_ctx":
+        p.mode = me.ME_MODE_PROPOSAL
+    elif case == "huge":
+        ref = _frame(me, h=70000, w=64)
+        cur = _frame(me, h=70000, w=64)
+    assert _est(me, ref, cur, p, mv, sad) == status
+    assert len(me._me_last_error()) > 0
+
+
+@pytest.mark.parametrize("case,status", [
+    ("null", 1), ("dtype", 1), ("empty", 1), ("nonsquare", 2), ("cell_not_dividing", 2), ("overlap", 1),
+    ("bad_block", 2), ("odd_frame", 1),
+])
+def test_warp_validation(me, case, status):
+    args = dict(z=FAKE, out=FAKE + (1 << 30), dt=0, C=4, Hf=135, Wf=240, mv=FAKE, block=16, fh=1080, fw=1920)
+    if case == "null":
+        args["z"] = 0
+    elif case == "dtype":
+        args["dt"] = 5
+    elif case == "empty":
+        args["C"] = 0
+    elif case == "nonsquare":
+        args["Wf"] = 480
+    elif case == "cell_not_dividing":
+        args.update(Hf=45, Wf=80, block=8)       # s = 12 does not divide 8
+    elif case == "overlap":
+        args["out"] = FAKE + 16
+    elif case == "bad_block":
+        args["block"] = 24
+    elif case == "odd_frame":
+        args["fh"] = 1081
+    r = me._me_warp_features(None, args["z"], args["out"], args["dt"], args["C"], args["Hf"], args["Wf"], args["mv"],
+                             args["block"], args["fh"], args["fw"], None)
+    assert r == status
+
+
+def test_stage_search_validation(me):
+    f = _frame(me)
+    assert me._me_stage_search(None, ctypes.byref(f), ctypes.byref(f), 16, 2, FAKE, 200, FAKE, FAKE, None) == 1
+    assert me._me_stage_search(None, ctypes.byref(f), ctypes.byref(f), 16, 70, None, 8, FAKE, FAKE, None) == 1
+    assert me._me_stage_search(None, ctypes.byref(f), ctypes.byref(f), 4, 2, None, 8, FAKE, FAKE, None) == 2
+
+
+def test_batch_validation(me):
+    assert me._me_batch_submit(None, None, 0, None) == 1
+    job = me.MeJob()
+    job.ref = _frame(me)
+    job.cur = _frame(me)
+    job.params = me.make_params(16, 8)
+    job.mv = 0
+    job.sad = FAKE
+    arr = (me.MeJob * 1)(job)
+    # a fake non-null context pointer is never dereferenced before job validation fails
+    assert me._me_batch_submit(ctypes.c_void_p(FAKE), arr, 1, None) == 1
+
+
+def test_ctx_create_null_out(me):
+    assert me._me_ctx_create(0, None) == 1
