@@ -30,22 +30,23 @@ struct SearchArgs {
     int32_t band_ty;        // candidate tile rows per LDS band
     int32_t lds_pitch;      // words per LDS window row (multiple of 4)
     int32_t col0, ncols;    // block columns covered by a launch without a list
+    int32_t nb;             // horizontally adjacent blocks per workgroup (1 with a list or predictors)
 };
 
 // Launch shape of the search kernel.
 struct TileCfg {
     int kx;        // horizontally adjacent candidates per lane
     int ky;        // vertically adjacent candidates per lane
-    int nw;        // waves per workgroup
+    int nb;        // blocks per workgroup (4 waves each)
     int band_ty;   // tile rows per LDS band
     int lds_pitch; // words per LDS row
     size_t lds_bytes;
 };
 
-// Fill in the LDS geometry of `cfg` (kx, ky, nw set) for block size B and a
-// candidate window of at most nx_max x ny_max; band_ty is the largest that
-// keeps the window within lds_cap bytes.  Returns false if no band fits.
-bool plan_tiles(int B, int nx_max, int ny_max, size_t lds_cap, TileCfg* cfg);
+// Fill in the LDS geometry of `cfg` (kx, ky, nb set) for block size B and
+// radius R; band_ty is the largest that keeps the window within lds_cap
+// bytes.  Returns false if no band fits.
+bool plan_tiles(int B, int R, size_t lds_cap, TileCfg* cfg);
 
 // Default launch shape for block size B and radius R.
 TileCfg default_tiles(int B, int R);

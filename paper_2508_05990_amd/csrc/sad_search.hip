@@ -2,16 +2,17 @@
 // (paper Sec. 3.2: SAD matching criterion, one thread group per block of the
 // current frame; Sec. 2.2: full search as the predictor-0 special case).
 //
-// One workgroup owns one block of the current frame.  Its candidate window of
-// the reference frame is staged in LDS (in dy bands when it does not fit);
-// the current block's rows are wave-uniform and go to SGPRs through scalar
-// loads; each lane owns a KY x KX tile of candidates (KX horizontally
-// adjacent), so one LDS segment of CW + KX - 1 words feeds CW * KX packed
-// v_sad_u16 operations, each of which adds |a-b| for the two 16-bit samples
-// of a word (one packed pixel column of one mosaic row).  The winner is the
-// minimum of a 64-bit key (SAD, dx^2+dy^2, dy, dx) -- a total order, so the
-// argmin is unique and independent of the reduction order: per lane, then a
-// wave butterfly, then across waves through LDS.
+// A workgroup owns nb horizontally adjacent blocks of the current frame, four
+// waves per block.  The union of their candidate windows in the reference
+// frame is staged in LDS (in dy bands when it does not fit), straight from
+// global memory to LDS.  The current block's rows are wave-uniform and reach
+// SGPRs through scalar loads.  Each lane owns a KY x KX tile of candidates
+// (KX horizontally adjacent), so one LDS segment of CW + KX - 1 words feeds
+// CW * KX packed v_sad_u16 operations, each of which adds |a-b| for the two
+// 16-bit samples of a word (one packed pixel column of one mosaic row).  The
+// winner is the minimum of a 64-bit key (SAD, dx^2+dy^2, dy, dx) -- a total
+// order, so the argmin is unique and independent of the reduction order: per
+// lane, then a wave butterfly, then across the block's waves through LDS.
 //
 // Blocks of full width take the register-tiled kernel; blocks cut by the
 // right frame edge (width < B) take a plain one-candidate-per-lane kernel.
@@ -21,9 +22,18 @@ namespace me {
 namespace {
 
 constexpr int kMaxWaves = 16;
+constexpr int kWavesPerBlock = 4;
+constexpr int kMaxPitch = 256;            // words per LDS row (four 64-word chunks)
+
+// The current frame is read-only for the whole launch and every read of it is
+// wave-uniform: reading it through the constant address space lets the
+// compiler use scalar loads into SGPRs (v_sad_u16 takes one SGPR operand).
+typedef const __attribute__((address_space(4))) uint32_t* cptr_t;
+
+__device__ __forceinline__ cptr_t as_const(const uint32_t* p) { return (cptr_t)(p); }
 
 // Workgroups are dispatched round-robin over the 8 XCDs; hand each XCD a
-// contiguous range of blocks so that neighbouring blocks, which read
+// contiguous range of work so that neighbouring blocks, which read
 // overlapping reference windows, share one L2.
 __device__ __forceinline__ int xcd_remap(int bid, int n)
 {
@@ -48,24 +58,14 @@ __device__ __forceinline__ uint64_t make_key(uint32_t sad, int dx, int dy)
     return (uint64_t)sad << 32 | lo;
 }
 
-// Block geometry and candidate rectangle of one workgroup.
+// Geometry and candidate rectangle of one block.
 struct BlockGeo {
     int blk, y0, x0, h, w;
     int dxlo, dxhi, dylo, dyhi;
 };
 
-// Resolve which block this workgroup owns; false if it owns none.
-__device__ __forceinline__ bool block_of(const SearchArgs& a, int B, BlockGeo& g)
+__device__ __forceinline__ void block_geo(const SearchArgs& a, int B, int blk, BlockGeo& g)
 {
-    int blk;
-    if (a.list) {
-        if ((int)blockIdx.x >= *a.list_n) return false;
-        blk = a.list[blockIdx.x];
-    } else {
-        const int lb = xcd_remap(blockIdx.x, gridDim.x);
-        const int bi = lb / a.ncols;
-        blk = bi * a.bw + a.col0 + (lb - bi * a.ncols);
-    }
     const int bi = blk / a.bw, bj = blk - bi * a.bw;
     g.blk = blk;
     g.y0 = bi * B;
@@ -82,57 +82,59 @@ __device__ __forceinline__ bool block_of(const SearchArgs& a, int B, BlockGeo& g
     g.dxhi = min(min(px + a.R, a.limit), a.Wp - g.x0 - g.w);
     g.dylo = max(max(py - a.R, -a.limit), -g.y0);
     g.dyhi = min(min(py + a.R, a.limit), a.Hp - g.y0 - g.h);
-    return true;
 }
 
-// Stage reference rows [grow0, grow0 + wrows) x words [gcol0, gcol0 + wcols)
-// into LDS, one wave per row; samples outside the frame read as zero (they
-// only ever meet candidates that are discarded).
+// Stage reference rows [grow0, grow0 + wrows) x words [gcol0, gcol0 + pitch)
+// into LDS, 64 words per wave instruction straight from global memory to LDS
+// (no register round trip, no wait per row).  Row addresses are wave-uniform;
+// the per-lane column offsets are the same for every row.  Positions outside
+// the frame load a clamped in-frame word: such words only ever meet
+// candidates that are discarded.  The caller waits (vmcnt) and barriers.
 __device__ __forceinline__ void stage_window(const SearchArgs& a, uint32_t* lds, int64_t grow0, int gcol0,
-                                             int wrows, int wcols, int wave, int nw, int lane)
+                                             int wrows, int wave, int nw, int lane)
 {
-    const int64_t rows_in = 2LL * a.Hp;
+    const int pitch = a.lds_pitch;
+    const int64_t rmax = 2LL * a.Hp - 1;
+    const int cmax = a.Wp - 1;
+    int gc[4];
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) gc[ch] = min(gcol0 + ch * 64 + lane, cmax);
     for (int rr = wave; rr < wrows; rr += nw) {
-        const int64_t gr = grow0 + rr;
-        const uint32_t* src = a.ref + gr * a.ref_pitch + gcol0;
-        uint32_t* dst = lds + rr * a.lds_pitch;
-        const bool row_in = gr < rows_in;
-        for (int cc = lane; cc < wcols; cc += 64) {
-            uint32_t v = 0u;
-            if (row_in && gcol0 + cc < a.Wp) v = src[cc];
-            dst[cc] = v;
+        const int64_t gr = min(grow0 + rr, rmax);
+        const uint32_t* src = a.ref + gr * a.ref_pitch;
+        uint32_t* dst = lds + rr * pitch;
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) {
+            if (ch * 64 < pitch && ch * 64 + lane < pitch)
+                __builtin_amdgcn_global_load_lds(src + gc[ch], dst + ch * 64, 4, 0, 0);
         }
     }
 }
 
-// Reduce the per-lane best keys of the workgroup and write the block result.
-__device__ __forceinline__ void finish(const SearchArgs& a, uint64_t best, int blk, uint64_t* red)
+__device__ __forceinline__ void write_result(const SearchArgs& a, int blk, uint64_t b)
 {
-    const int tid = threadIdx.x, nw = blockDim.x >> 6;
-    best = wave_min_u64(best);
-    if ((tid & 63) == 0) red[tid >> 6] = best;
-    __syncthreads();
-    if (tid == 0) {
-        uint64_t b = red[0];
-        for (int k = 1; k < nw; ++k) b = red[k] < b ? red[k] : b;
-        if (b == ~0ull) {
-            a.mv[2 * blk] = 0;
-            a.mv[2 * blk + 1] = 0;
-            a.sad[blk] = -1;
-        } else {
-            a.mv[2 * blk] = (int16_t)((int)(b & 0xffu) - 128);
-            a.mv[2 * blk + 1] = (int16_t)((int)((b >> 8) & 0xffu) - 128);
-            a.sad[blk] = (int32_t)(b >> 32);
-        }
+    if (b == ~0ull) {
+        a.mv[2 * blk] = 0;
+        a.mv[2 * blk + 1] = 0;
+        a.sad[blk] = -1;
+    } else {
+        a.mv[2 * blk] = (int16_t)((int)(b & 0xffu) - 128);
+        a.mv[2 * blk + 1] = (int16_t)((int)((b >> 8) & 0xffu) - 128);
+        a.sad[blk] = (int32_t)(b >> 32);
     }
 }
 
 // SADs of one lane's KY x KX candidate tile over the 2h mosaic rows of a
 // full-width block.  curp: first word of the block in the current frame;
-// lbase4: LDS position of the tile's first candidate for block row 0.
+// lbase4: LDS position of the tile's first candidate for block row 0; the
+// tile's candidate rows are adjacent, so block row r of candidate row j reads
+// LDS row r + 2j.  Walking the block rows of one parity in steps of 2, each
+// LDS row is loaded once and kept in a ring of KY segments for the KY
+// candidate rows that use it; the next ring slot and the next current-block
+// row are requested a step ahead of their use.
 template <int CW, int NCH, int KX, int KY>
-__device__ __forceinline__ void tile_sads(const uint32_t* __restrict__ curp, int64_t cur_pitch, int rows2,
-                                          const uint4* __restrict__ lbase4, int pitch4, uint32_t (&acc)[KY][KX])
+__device__ __forceinline__ void tile_sads(cptr_t curp, int64_t cur_pitch, int h, const uint4* __restrict__ lbase4,
+                                          int pitch4, uint32_t (&acc)[KY][KX])
 {
     constexpr int SEGV = (CW + KX - 1 + 3) / 4;
 #pragma unroll
@@ -140,99 +142,278 @@ __device__ __forceinline__ void tile_sads(const uint32_t* __restrict__ curp, int
 #pragma unroll
         for (int i = 0; i < KX; ++i) acc[j][i] = 0u;
 
-    for (int r = 0; r < rows2; ++r) {
-        const uint32_t* crow = curp + r * cur_pitch;
+#pragma unroll 1
+    for (int q = 0; q < NCH; ++q) {
+#pragma unroll 1
+        for (int par = 0; par < 2; ++par) {
+            const uint4* col4 = lbase4 + par * pitch4 + (q * CW) / 4;   // LDS row par, chunk q
+            cptr_t ccol = curp + par * cur_pitch + q * CW;                 // block row par, chunk q
+            uint4 ring[KY][SEGV];
 #pragma unroll
-        for (int q = 0; q < NCH; ++q) {
+            for (int t = 0; t < KY - 1; ++t)
+#pragma unroll
+                for (int v = 0; v < SEGV; ++v) ring[t][v] = col4[(2 * t) * pitch4 + v];
             uint32_t c[CW];
 #pragma unroll
-            for (int k = 0; k < CW; ++k) c[k] = crow[q * CW + k];
+            for (int k = 0; k < CW; ++k) c[k] = ccol[k];
+#pragma unroll 1
+            for (int step = 0; step < h; step += KY) {
 #pragma unroll
-            for (int j = 0; j < KY; ++j) {
-                const uint4* l4 = lbase4 + (r + 2 * j) * pitch4 + (q * CW) / 4;
-                uint32_t seg[SEGV * 4];
+                for (int u = 0; u < KY; ++u) {
+                    const int st = step + u;               // block row par + 2 st
+                    if (st < h) {
 #pragma unroll
-                for (int v = 0; v < SEGV; ++v) {
-                    const uint4 t = l4[v];
-                    seg[4 * v + 0] = t.x;
-                    seg[4 * v + 1] = t.y;
-                    seg[4 * v + 2] = t.z;
-                    seg[4 * v + 3] = t.w;
+                        for (int v = 0; v < SEGV; ++v)
+                            ring[(u + KY - 1) % KY][v] = col4[(2 * (st + KY - 1)) * pitch4 + v];
+                        uint32_t cn[CW];
+                        const int stn = st + 1 < h ? st + 1 : st;
+#pragma unroll
+                        for (int k = 0; k < CW; ++k) cn[k] = ccol[(2 * stn) * cur_pitch + k];
+#pragma unroll
+                        for (int j = 0; j < KY; ++j) {
+                            uint32_t seg[SEGV * 4];
+#pragma unroll
+                            for (int v = 0; v < SEGV; ++v) {
+                                const uint4 t4 = ring[(u + j) % KY][v];
+                                seg[4 * v + 0] = t4.x;
+                                seg[4 * v + 1] = t4.y;
+                                seg[4 * v + 2] = t4.z;
+                                seg[4 * v + 3] = t4.w;
+                            }
+#pragma unroll
+                            for (int k = 0; k < CW; ++k)
+#pragma unroll
+                                for (int i = 0; i < KX; ++i)
+                                    acc[j][i] = __builtin_amdgcn_sad_u16(c[k], seg[k + i], acc[j][i]);
+                        }
+#pragma unroll
+                        for (int k = 0; k < CW; ++k) c[k] = cn[k];
+                    }
                 }
-#pragma unroll
-                for (int k = 0; k < CW; ++k)
-#pragma unroll
-                    for (int i = 0; i < KX; ++i) acc[j][i] = __builtin_amdgcn_sad_u16(c[k], seg[k + i], acc[j][i]);
             }
         }
     }
 }
 
-template <int CW, int NCH, int KX, int KY>
-__global__ __launch_bounds__(kMaxWaves * 64) void sad_search_kernel(SearchArgs a)
+// One candidate per lane with a 16-byte aligned LDS column (b128 reads).
+template <int CW, int NCH>
+__device__ __forceinline__ uint32_t single_sad_aligned(cptr_t curp, int64_t cur_pitch, int rows2,
+                                                       const uint4* __restrict__ lbase4, int pitch4)
 {
-    extern __shared__ uint4 lds4[];
-    __shared__ uint64_t red[kMaxWaves];
-    constexpr int B = CW * NCH;
-    BlockGeo g;
-    if (!block_of(a, B, g)) return;
-    if (g.w != B) return;                      // partial-width blocks: generic kernel
-    uint32_t* lds = reinterpret_cast<uint32_t*>(lds4);
-    const int tid = threadIdx.x;
-    const int nt = blockDim.x, nw = nt >> 6;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int lane = tid & 63;
-    const int pitch4 = a.lds_pitch >> 2;
-
-    uint64_t best = ~0ull;
-    if (g.dxlo <= g.dxhi && g.dylo <= g.dyhi) {
-        const int nx = g.dxhi - g.dxlo + 1, ny = g.dyhi - g.dylo + 1;
-        const int txn = (nx + KX - 1) / KX, tyn = (ny + KY - 1) / KY;
-        const int wcols = B + txn * KX - 1;
-        const uint32_t* curp = a.cur + 2LL * g.y0 * a.cur_pitch + g.x0;
-        for (int ty0 = 0; ty0 < tyn; ty0 += a.band_ty) {
-            const int bty = min(a.band_ty, tyn - ty0);
-            __syncthreads();
-            stage_window(a, lds, 2LL * (g.y0 + g.dylo + ty0 * KY), g.x0 + g.dxlo, 2 * (g.h + bty * KY - 1), wcols,
-                         wave, nw, lane);
-            __syncthreads();
-            const int ntiles = txn * bty;
-            for (int t0 = wave * 64; t0 < ntiles; t0 += nt) {
-                const int t = t0 + lane;
-                const bool active = t < ntiles;
-                const int tt = active ? t : t0;
-                const int tyl = tt / txn, tx = tt - tyl * txn;
-                const uint4* lbase4 = lds4 + (2 * tyl * KY) * pitch4 + (tx * KX) / 4;
-                uint32_t acc[KY][KX];
-                tile_sads<CW, NCH, KX, KY>(curp, a.cur_pitch, 2 * g.h, lbase4, pitch4, acc);
-                if (active) {
+    uint32_t s = 0u;
+    for (int r = 0; r < rows2; ++r) {
+        cptr_t crow = curp + r * cur_pitch;
+        const uint4* l4 = lbase4 + r * pitch4;
 #pragma unroll
-                    for (int j = 0; j < KY; ++j)
+        for (int q = 0; q < NCH; ++q) {
 #pragma unroll
-                        for (int i = 0; i < KX; ++i) {
-                            const int dx = g.dxlo + tx * KX + i;
-                            const int dy = g.dylo + (ty0 + tyl) * KY + j;
-                            if (dx <= g.dxhi && dy <= g.dyhi) {
-                                const uint64_t key = make_key(acc[j][i], dx, dy);
-                                best = key < best ? key : best;
-                            }
-                        }
-                }
+            for (int v = 0; v < CW / 4; ++v) {
+                const uint4 t = l4[q * (CW / 4) + v];
+                s = __builtin_amdgcn_sad_u16(crow[q * CW + 4 * v + 0], t.x, s);
+                s = __builtin_amdgcn_sad_u16(crow[q * CW + 4 * v + 1], t.y, s);
+                s = __builtin_amdgcn_sad_u16(crow[q * CW + 4 * v + 2], t.z, s);
+                s = __builtin_amdgcn_sad_u16(crow[q * CW + 4 * v + 3], t.w, s);
             }
         }
     }
-    finish(a, best, g.blk, red);
+    return s;
+}
+
+// One candidate per lane at any LDS column (word reads).
+template <int CW>
+__device__ __forceinline__ uint32_t single_sad_full(cptr_t curp, int64_t cur_pitch, int rows2, int nch,
+                                                    const uint32_t* __restrict__ lbase, int pitch)
+{
+    uint32_t s = 0u;
+    for (int r = 0; r < rows2; ++r) {
+        cptr_t crow = curp + r * cur_pitch;
+        const uint32_t* lrow = lbase + r * pitch;
+        for (int q = 0; q < nch; ++q) {
+#pragma unroll
+            for (int k = 0; k < CW; ++k) s = __builtin_amdgcn_sad_u16(crow[q * CW + k], lrow[q * CW + k], s);
+        }
+    }
+    return s;
+}
+
+// One candidate per lane over a block of runtime width w.
+__device__ __forceinline__ uint32_t single_sad(cptr_t curp, int64_t cur_pitch, int rows2, int w,
+                                               const uint32_t* __restrict__ lbase, int pitch)
+{
+    uint32_t s = 0u;
+    for (int r = 0; r < rows2; ++r) {
+        cptr_t crow = curp + r * cur_pitch;
+        const uint32_t* lrow = lbase + r * pitch;
+        for (int k = 0; k < w; ++k) s = __builtin_amdgcn_sad_u16(crow[k], lrow[k], s);
+    }
+    return s;
+}
+
+// Candidates of one block within one dy band, as wave tasks of 64 lanes:
+//   main   KY x KX tiles over the first mx = nx - nx % KX columns and the
+//          first my = nyb - nyb % KY rows;
+//   rows   KX x 1 tiles over the last nyb % KY rows, all columns (the last
+//          tile of a row may stick out and is masked);
+//   single one candidate per lane over the last nx % KX columns of the first
+//          my rows.
+// The block's waves take the tasks round-robin, starting at a wave that
+// rotates with the block index so the short extra tasks spread over SIMDs.
+// lds: LDS word of the block's candidate (dxlo, band row 0) for block row 0.
+template <int CW, int NCH, int KX, int KY>
+__device__ __forceinline__ void block_band(const SearchArgs& a, const BlockGeo& g, int y0c, int nyb, int wib,
+                                           const uint32_t* lds, int pitch, int lane, uint64_t& best)
+{
+    const uint4* lds4 = reinterpret_cast<const uint4*>(lds);
+    const int pitch4 = pitch >> 2;
+    const int nx = g.dxhi - g.dxlo + 1;
+    const int txn = nx / KX, mx = txn * KX, rx = nx - mx;
+    const int txr = (nx + KX - 1) / KX;
+    const int tyn = nyb / KY, myb = tyn * KY, ryb = nyb - myb;
+    const int n_main = txn * tyn;
+    const int n_rows = txr * ryb;
+    const int n_single = rx * myb;
+    const int t_main = (n_main + 63) >> 6;
+    const int t_rows = t_main + ((n_rows + 63) >> 6);
+    const int tasks = t_rows + ((n_single + 63) >> 6);
+    cptr_t curp = as_const(a.cur + 2LL * g.y0 * a.cur_pitch + g.x0);
+    const int first = (wib + kWavesPerBlock - g.blk % kWavesPerBlock) % kWavesPerBlock;
+    for (int task = first; task < tasks; task += kWavesPerBlock) {
+        if (task < t_main) {
+            const int t = task * 64 + lane;
+            const bool active = t < n_main;
+            const int tt = active ? t : task * 64;
+            const int tyl = tt / txn, tx = tt - tyl * txn;
+            uint32_t acc[KY][KX];
+            tile_sads<CW, NCH, KX, KY>(curp, a.cur_pitch, g.h, lds4 + (2 * tyl * KY) * pitch4 + (tx * KX) / 4, pitch4,
+                                       acc);
+            if (active) {
+#pragma unroll
+                for (int j = 0; j < KY; ++j)
+#pragma unroll
+                    for (int i = 0; i < KX; ++i) {
+                        const uint64_t key = make_key(acc[j][i], g.dxlo + tx * KX + i, g.dylo + y0c + tyl * KY + j);
+                        best = key < best ? key : best;
+                    }
+            }
+        } else if (task < t_rows) {
+            const int t = (task - t_main) * 64 + lane;
+            const bool active = t < n_rows;
+            const int tt = active ? t : (task - t_main) * 64;
+            const int ry = tt / txr, tx = tt - ry * txr;
+            const int cy = myb + ry;
+            uint32_t acc[1][KX];
+            tile_sads<CW, NCH, KX, 1>(curp, a.cur_pitch, g.h, lds4 + (2 * cy) * pitch4 + (tx * KX) / 4, pitch4, acc);
+            if (active) {
+#pragma unroll
+                for (int i = 0; i < KX; ++i) {
+                    if (tx * KX + i < nx) {
+                        const uint64_t key = make_key(acc[0][i], g.dxlo + tx * KX + i, g.dylo + y0c + cy);
+                        best = key < best ? key : best;
+                    }
+                }
+            }
+        } else {
+            const int t = (task - t_rows) * 64 + lane;
+            const bool active = t < n_single;
+            const int tt = active ? t : (task - t_rows) * 64;
+            const int cy = tt / rx, cx = mx + (tt - cy * rx);
+            uint32_t sad;
+            if (rx == 1)                               // the column is 16-byte aligned (mx % 4 == 0)
+                sad = single_sad_aligned<CW, NCH>(curp, a.cur_pitch, 2 * g.h, lds4 + (2 * cy) * pitch4 + cx / 4,
+                                                  pitch4);
+            else
+                sad = single_sad_full<CW>(curp, a.cur_pitch, 2 * g.h, NCH, lds + 2 * cy * pitch + cx, pitch);
+            if (active) {
+                const uint64_t key = make_key(sad, g.dxlo + cx, g.dylo + y0c + cy);
+                best = key < best ? key : best;
+            }
+        }
+    }
+}
+
+// Full-width blocks, nb per workgroup (nb = 1 when a block list or per-block
+// predictors are given, since their candidate rows then differ).
+template <int CW, int NCH, int KX, int KY>
+__global__ __launch_bounds__(512) void sad_search_kernel(SearchArgs a)
+{
+    extern __shared__ uint4 lds_dyn[];
+    __shared__ uint64_t red[kMaxWaves];
+    constexpr int B = CW * NCH;
+    uint32_t* lds = reinterpret_cast<uint32_t*>(lds_dyn);
+    const int tid = threadIdx.x;
+    const int nw = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int pitch = a.lds_pitch;
+
+    // blocks of this workgroup: [first_blk, first_blk + nblk), one block row
+    int first_blk, nblk;
+    if (a.list) {
+        if ((int)blockIdx.x >= *a.list_n) return;     // whole workgroup leaves
+        first_blk = a.list[blockIdx.x];
+        nblk = 1;
+    } else {
+        const int groups = (a.ncols + a.nb - 1) / a.nb;
+        const int gid = xcd_remap(blockIdx.x, gridDim.x);
+        const int bi = gid / groups, gj = gid - bi * groups;
+        const int c0 = gj * a.nb;
+        first_blk = bi * a.bw + a.col0 + c0;
+        nblk = min(a.nb, a.ncols - c0);
+    }
+    BlockGeo g0;
+    block_geo(a, B, first_blk, g0);
+    if (g0.w != B) return;                        // partial-width blocks: generic kernel
+
+    const int mine = wave / kWavesPerBlock;         // this wave's block within the group
+    const int wib = wave - mine * kWavesPerBlock;
+    const bool has_block = mine < nblk;
+    BlockGeo g;
+    block_geo(a, B, first_blk + (has_block ? mine : 0), g);
+    const int left = g0.x0 + g0.dxlo;               // frame column of LDS column 0
+
+    uint64_t best = ~0ull;
+    // the blocks of a group share y0, h and (without predictors) the dy range
+    if (g0.dylo <= g0.dyhi && g0.dxlo <= g0.dxhi) {
+        const int ny = g0.dyhi - g0.dylo + 1;
+        const int band = a.band_ty * KY;            // candidate rows per band (multiple of KY)
+        for (int y0c = 0; y0c < ny; y0c += band) {
+            const int nyb = min(band, ny - y0c);
+            __syncthreads();
+            stage_window(a, lds, 2LL * (g0.y0 + g0.dylo + y0c), left, 2 * (g0.h + nyb - 1), wave, nw, lane);
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            if (has_block && g.dxlo <= g.dxhi)
+                block_band<CW, NCH, KX, KY>(a, g, y0c, nyb, wib, lds + (g.x0 + g.dxlo - left), pitch, lane, best);
+        }
+    }
+    best = wave_min_u64(best);
+    if (lane == 0) red[wave] = best;
+    __syncthreads();
+    if (has_block && wib == 0 && lane == 0) {
+        uint64_t b = red[wave];
+        for (int k = 1; k < kWavesPerBlock; ++k) b = red[wave + k] < b ? red[wave + k] : b;
+        write_result(a, g.blk, b);
+    }
 }
 
 // Blocks cut by the right frame edge: one candidate per lane, runtime width.
 __global__ __launch_bounds__(256) void sad_search_generic(SearchArgs a)
 {
-    extern __shared__ uint4 lds4[];
+    extern __shared__ uint4 lds_dyn[];
     __shared__ uint64_t red[kMaxWaves];
+    int blk;
+    if (a.list) {
+        if ((int)blockIdx.x >= *a.list_n) return;
+        blk = a.list[blockIdx.x];
+    } else {
+        const int lb = xcd_remap(blockIdx.x, gridDim.x);
+        const int bi = lb / a.ncols;
+        blk = bi * a.bw + a.col0 + (lb - bi * a.ncols);
+    }
     BlockGeo g;
-    if (!block_of(a, a.block, g)) return;
-    if (g.w == a.block) return;                // full-width blocks: tiled kernel
-    uint32_t* lds = reinterpret_cast<uint32_t*>(lds4);
+    block_geo(a, a.block, blk, g);
+    if (g.w == a.block) return;                    // full-width blocks: tiled kernel
+    uint32_t* lds = reinterpret_cast<uint32_t*>(lds_dyn);
     const int tid = threadIdx.x;
     const int nt = blockDim.x, nw = nt >> 6;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -241,28 +422,30 @@ __global__ __launch_bounds__(256) void sad_search_generic(SearchArgs a)
     uint64_t best = ~0ull;
     if (g.dxlo <= g.dxhi && g.dylo <= g.dyhi) {
         const int nx = g.dxhi - g.dxlo + 1, ny = g.dyhi - g.dylo + 1;
-        const int wcols = g.w + nx - 1;
-        const uint32_t* curp = a.cur + 2LL * g.y0 * a.cur_pitch + g.x0;
+        cptr_t curp = as_const(a.cur + 2LL * g.y0 * a.cur_pitch + g.x0);
         for (int y0c = 0; y0c < ny; y0c += a.band_ty) {
             const int nyb = min(a.band_ty, ny - y0c);
             __syncthreads();
-            stage_window(a, lds, 2LL * (g.y0 + g.dylo + y0c), g.x0 + g.dxlo, 2 * (g.h + nyb - 1), wcols, wave, nw,
-                         lane);
+            stage_window(a, lds, 2LL * (g.y0 + g.dylo + y0c), g.x0 + g.dxlo, 2 * (g.h + nyb - 1), wave, nw, lane);
+            __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
             for (int cand = tid; cand < nx * nyb; cand += nt) {
                 const int cy = cand / nx, cx = cand - cy * nx;
-                uint32_t s = 0u;
-                for (int r = 0; r < 2 * g.h; ++r) {
-                    const uint32_t* crow = curp + r * a.cur_pitch;
-                    const uint32_t* lrow = lds + (r + 2 * cy) * a.lds_pitch + cx;
-                    for (int k = 0; k < g.w; ++k) s = __builtin_amdgcn_sad_u16(crow[k], lrow[k], s);
-                }
+                const uint32_t s =
+                    single_sad(curp, a.cur_pitch, 2 * g.h, g.w, lds + 2 * cy * a.lds_pitch + cx, a.lds_pitch);
                 const uint64_t key = make_key(s, g.dxlo + cx, g.dylo + y0c + cy);
                 best = key < best ? key : best;
             }
         }
     }
-    finish(a, best, g.blk, red);
+    best = wave_min_u64(best);
+    if (lane == 0) red[wave] = best;
+    __syncthreads();
+    if (tid == 0) {
+        uint64_t b = red[0];
+        for (int k = 1; k < nw; ++k) b = red[k] < b ? red[k] : b;
+        write_result(a, blk, b);
+    }
 }
 
 using KernelFn = void (*)(SearchArgs);
@@ -290,7 +473,8 @@ KernelFn kernel_for(int B, int kx, int ky)
     }
 }
 
-constexpr size_t kLdsCap = 64 * 1024;    // preferred window size: leaves room for 2 workgroups per CU
+constexpr size_t kLdsCap = 53 * 1024;    // preferred: 3 workgroups per CU
+constexpr size_t kLdsMid = 80 * 1024;    // 2 workgroups per CU
 constexpr size_t kLdsMax = 160 * 1024;   // gfx950 LDS per workgroup
 
 hipError_t set_lds(const void* k, size_t bytes)
@@ -299,25 +483,46 @@ hipError_t set_lds(const void* k, size_t bytes)
     return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// Words per LDS row of the tiled kernel for nb blocks and a candidate window
+// of up to n x n: block b's window starts at most b*B words in, and needs
+// both its single-candidate reads (n + B - 1 words) and its widest tile
+// segment read.  An odd number of 16-byte quads per row spreads lanes that
+// read one column of rows 2 apart over the LDS banks.
+int tiled_pitch(int B, int n, int kx, int nb)
+{
+    const int CW = B < 16 ? B : 16;
+    const int NCH = B / CW;
+    const int segv = (CW + kx - 1 + 3) / 4;
+    const int txr = (n + kx - 1) / kx;             // tiles per row, including a partial last one
+    int pitch = n + B - 1;
+    const int read_end = (txr - 1) * kx + (NCH - 1) * CW + 4 * segv;
+    if (read_end > pitch) pitch = read_end;
+    pitch += (nb - 1) * B;
+    pitch = (pitch + 3) & ~3;
+    if (((pitch >> 2) & 1) == 0) pitch += 4;
+    return pitch;
+}
+
+size_t tiled_bytes(int B, int n, int ky, int band_ty, int pitch)
+{
+    int rows = band_ty * ky;
+    if (rows > n) rows = n;
+    return (size_t)2 * (B + rows - 1) * pitch * 4;
+}
+
 }  // namespace
 
 bool tiles_supported(int B, int kx, int ky) { return kernel_for(B, kx, ky) != nullptr; }
 
-bool plan_tiles(int B, int nx_max, int ny_max, size_t lds_cap, TileCfg* cfg)
+bool plan_tiles(int B, int R, size_t lds_cap, TileCfg* cfg)
 {
-    const int CW = B < 16 ? B : 16;
-    const int NCH = B / CW;
-    const int kx = cfg->kx, ky = cfg->ky;
-    const int txn = (nx_max + kx - 1) / kx, tyn = (ny_max + ky - 1) / ky;
-    const int segv = (CW + kx - 1 + 3) / 4;
-    int pitch = B + txn * kx - 1;
-    const int read_end = (txn - 1) * kx + (NCH - 1) * CW + 4 * segv;
-    if (read_end > pitch) pitch = read_end;
-    pitch = (pitch + 3) & ~3;
-    if (pitch % 32 == 0) pitch += 4;   // rows of a band start on different banks
-    int band = tyn;
-    while (band > 1 && (size_t)2 * (B + band * ky - 1) * pitch * 4 > lds_cap) --band;
-    const size_t bytes = (size_t)2 * (B + band * ky - 1) * pitch * 4;
+    const int n = 2 * R + 1;
+    if (cfg->nb < 1 || cfg->nb * kWavesPerBlock > kMaxWaves) return false;
+    const int pitch = tiled_pitch(B, n, cfg->kx, cfg->nb);
+    if (pitch > kMaxPitch) return false;
+    int band = (n + cfg->ky - 1) / cfg->ky;
+    while (band > 1 && tiled_bytes(B, n, cfg->ky, band, pitch) > lds_cap) --band;
+    const size_t bytes = tiled_bytes(B, n, cfg->ky, band, pitch);
     if (bytes > lds_cap) return false;
     cfg->band_ty = band;
     cfg->lds_pitch = pitch;
@@ -328,33 +533,41 @@ bool plan_tiles(int B, int nx_max, int ny_max, size_t lds_cap, TileCfg* cfg)
 TileCfg default_tiles(int B, int R)
 {
     TileCfg c{};
-    c.kx = 8;
-    c.ky = 2;
-    const int n = 2 * R + 1;
-    const int tiles = ((n + c.kx - 1) / c.kx) * ((n + c.ky - 1) / c.ky);
-    const int nw = (tiles + 63) / 64;
-    c.nw = nw < 1 ? 1 : (nw > 8 ? 8 : nw);
-    if (!plan_tiles(B, n, n, kLdsCap, &c)) plan_tiles(B, n, n, kLdsMax, &c);
+    c.kx = 4;
+    c.ky = 4;
+    // two blocks per workgroup share one window when the radius keeps their
+    // window starts 16-byte aligned (R % 4 == 0) and the window fits in a
+    // single band within 80 KB
+    if (R % 4 == 0) {
+        c.nb = 2;
+        if (plan_tiles(B, R, kLdsMid, &c) && c.band_ty * c.ky >= 2 * R + 1) return c;
+    }
+    c.nb = 1;
+    if (plan_tiles(B, R, kLdsCap, &c) || plan_tiles(B, R, kLdsMid, &c) || plan_tiles(B, R, kLdsMax, &c)) return c;
     return c;
 }
 
-hipError_t launch_sad_search(const SearchArgs& a, const TileCfg& cfg, int n_wg, hipStream_t stream)
+hipError_t launch_sad_search(const SearchArgs& a, const TileCfg& cfg_in, int n_wg, hipStream_t stream)
 {
-    KernelFn k = kernel_for(a.block, cfg.kx, cfg.ky);
-    if (!k || cfg.nw < 1 || cfg.nw > kMaxWaves || (cfg.lds_pitch & 3)) return hipErrorInvalidValue;
-    const int n = 2 * a.R + 1;
-    {   // the shape must cover the widest candidate window of this radius
-        TileCfg need = cfg;
-        if (!plan_tiles(a.block, n, n, cfg.lds_bytes, &need) || need.lds_pitch > cfg.lds_pitch ||
-            (size_t)2 * (a.block + cfg.band_ty * cfg.ky - 1) * cfg.lds_pitch * 4 > cfg.lds_bytes)
+    TileCfg cfg = cfg_in;
+    if ((a.list || a.pred || (a.R % 4) != 0) && cfg.nb != 1) {   // one block per workgroup
+        cfg.nb = 1;
+        if (!plan_tiles(a.block, a.R, kLdsCap, &cfg) && !plan_tiles(a.block, a.R, kLdsMid, &cfg) &&
+            !plan_tiles(a.block, a.R, kLdsMax, &cfg))
             return hipErrorInvalidValue;
     }
+    KernelFn k = kernel_for(a.block, cfg.kx, cfg.ky);
+    if (!k || cfg.nb < 1 || cfg.nb * kWavesPerBlock > kMaxWaves || (cfg.lds_pitch & 3)) return hipErrorInvalidValue;
+    const int n = 2 * a.R + 1;
+    // the shape must cover the widest candidate window of this radius
+    if (cfg.band_ty < 1 || cfg.lds_pitch > kMaxPitch || cfg.lds_pitch < tiled_pitch(a.block, n, cfg.kx, cfg.nb) ||
+        tiled_bytes(a.block, n, cfg.ky, cfg.band_ty, cfg.lds_pitch) > cfg.lds_bytes || cfg.lds_bytes > kLdsMax)
+        return hipErrorInvalidValue;
     const int full_cols = a.Wp / a.block;           // block columns of full width
     const bool has_partial = full_cols < a.bw;
 
     // generic kernel: one candidate per lane, LDS rows of w + n - 1 words
-    int gpitch = ((a.block + n - 1) + 3) & ~3;
-    if (gpitch % 32 == 0) gpitch += 4;
+    const int gpitch = ((a.block + n - 1) + 3) & ~3;
     int gband = n;
     while (gband > 1 && (size_t)2 * (a.block + gband - 1) * gpitch * 4 > kLdsCap) --gband;
     size_t gbytes = (size_t)2 * (a.block + gband - 1) * gpitch * 4;
@@ -363,9 +576,8 @@ hipError_t launch_sad_search(const SearchArgs& a, const TileCfg& cfg, int n_wg, 
         while (gband > 1 && (size_t)2 * (a.block + gband - 1) * gpitch * 4 > kLdsMax) --gband;
         gbytes = (size_t)2 * (a.block + gband - 1) * gpitch * 4;
     }
-    if (has_partial && gbytes > kLdsMax) return hipErrorInvalidValue;
+    if (has_partial && (gbytes > kLdsMax || gpitch > kMaxPitch)) return hipErrorInvalidValue;
 
-    if (cfg.lds_bytes > kLdsMax) return hipErrorInvalidValue;
     hipError_t e = set_lds(reinterpret_cast<const void*>(k), cfg.lds_bytes);
     if (e != hipSuccess) return e;
     if (has_partial) {
@@ -375,26 +587,24 @@ hipError_t launch_sad_search(const SearchArgs& a, const TileCfg& cfg, int n_wg, 
     SearchArgs b = a;
     b.band_ty = cfg.band_ty;
     b.lds_pitch = cfg.lds_pitch;
+    b.nb = cfg.nb;
+    SearchArgs c = a;
+    c.band_ty = gband;
+    c.lds_pitch = gpitch;
+    c.nb = 1;
     if (a.list) {
         if (n_wg <= 0) return hipSuccess;
-        hipLaunchKernelGGL(k, dim3(n_wg), dim3(cfg.nw * 64), cfg.lds_bytes, stream, b);
-        if (has_partial) {
-            SearchArgs c = a;
-            c.band_ty = gband;
-            c.lds_pitch = gpitch;
-            hipLaunchKernelGGL(sad_search_generic, dim3(n_wg), dim3(256), gbytes, stream, c);
-        }
+        hipLaunchKernelGGL(k, dim3(n_wg), dim3(kWavesPerBlock * 64), cfg.lds_bytes, stream, b);
+        if (has_partial) hipLaunchKernelGGL(sad_search_generic, dim3(n_wg), dim3(256), gbytes, stream, c);
         return hipGetLastError();
     }
     if (full_cols > 0) {
         b.col0 = 0;
         b.ncols = full_cols;
-        hipLaunchKernelGGL(k, dim3(a.bh * full_cols), dim3(cfg.nw * 64), cfg.lds_bytes, stream, b);
+        const int groups = (full_cols + cfg.nb - 1) / cfg.nb;
+        hipLaunchKernelGGL(k, dim3(a.bh * groups), dim3(cfg.nb * kWavesPerBlock * 64), cfg.lds_bytes, stream, b);
     }
     if (has_partial) {
-        SearchArgs c = a;
-        c.band_ty = gband;
-        c.lds_pitch = gpitch;
         c.col0 = full_cols;
         c.ncols = 1;
         hipLaunchKernelGGL(sad_search_generic, dim3(a.bh), dim3(256), gbytes, stream, c);
