@@ -146,6 +146,32 @@ me_status me_warp_features(me_ctx ctx, const void* z_ref, void* z_out, int32_t d
                            int32_t Wf, const int16_t* mv, int32_t block, int32_t frame_h, int32_t frame_w,
                            void* stream);
 
+/*
+ * me_refine -- refine-and-fallback step of the learned-proposal mode, given
+ * the proposal network's per-block output.  The proposal network is this
+ * library's addition: the paper's own learned part corrects features
+ * (Sec. 3.3), not vectors.  The selection rule is still the paper's lowest
+ * SAD (Sec. 3.2) over an exact search, so every output vector is either the
+ * exact result of a small search around the proposal or the full-search
+ * result.
+ *
+ * net_out : device float32 [3][bh][bw]: mvx, mvy (units of 8 packed pixels)
+ *           and a confidence logit, per block.
+ * Steps   : p = clamp(rint(8*o), -radius, radius) (ties to even); exact
+ *           search of radius params->refine_radius around p, candidates
+ *           limited to |dx|, |dy| <= radius; fallback to full search of
+ *           params->radius when logit < conf_logit_thresh, or the refined
+ *           SAD > floor(sad_ratio * M * n) (n = samples in the block, M =
+ *           sad_median_per_sample or, if that is <= 0, the value loaded with
+ *           the weights; the product is taken in double, left to right), or
+ *           the refine window has no valid candidate.
+ * mv, sad : device outputs as in me_estimate; fallback: device uint8
+ *           [bh][bw] or NULL (1 = fell back).
+ * Needs a context (scratch buffers live there); ME_E_STATE if no M is known.
+ */
+me_status me_refine(me_ctx ctx, const me_frame* ref, const me_frame* cur, const me_params* params,
+                    const float* net_out, int16_t* mv, int32_t* sad, uint8_t* fallback, void* stream);
+
 /* One frame pair of a batch (me_batch_submit). */
 typedef struct {
     me_frame ref;

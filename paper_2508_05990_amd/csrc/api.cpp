@@ -90,9 +90,48 @@ struct me_ctx_s {
     std::mutex mu;
     // launch shapes picked by the tuner, keyed by (B, R, Hp, Wp)
     std::map<std::tuple<int, int, int, int>, TileCfg> tuned;
+    // proposal-mode scratch, grown on demand: decoded proposals, fallback
+    // flags, the compacted fallback list and its device count
+    int16_t* pred = nullptr;
+    uint8_t* fb = nullptr;
+    int32_t* list = nullptr;
+    int32_t* count = nullptr;
+    size_t cap_blocks = 0;
+    // SAD per sample of the exhaustive best match, median over training data
+    float median_per_sample = 0.0f;
+
+    ~me_ctx_s()
+    {
+        (void)hipFree(pred);
+        (void)hipFree(fb);
+        (void)hipFree(list);
+        (void)hipFree(count);
+    }
 };
 
 namespace {
+
+me_status ensure_scratch(me_ctx ctx, size_t nblk)
+{
+    if (nblk <= ctx->cap_blocks) return ME_OK;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    (void)hipFree(ctx->pred);
+    (void)hipFree(ctx->fb);
+    (void)hipFree(ctx->list);
+    (void)hipFree(ctx->count);
+    ctx->pred = nullptr;
+    ctx->fb = nullptr;
+    ctx->list = nullptr;
+    ctx->count = nullptr;
+    ctx->cap_blocks = 0;
+    if (hipMalloc(&ctx->pred, nblk * 2 * sizeof(int16_t)) != hipSuccess ||
+        hipMalloc(&ctx->fb, nblk) != hipSuccess || hipMalloc(&ctx->list, nblk * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&ctx->count, sizeof(int32_t)) != hipSuccess)
+        return fail(ME_E_NOMEM, "proposal scratch: device allocation of %zu blocks failed", nblk);
+    ctx->cap_blocks = nblk;
+    return ME_OK;
+}
 
 TileCfg tiles_for(me_ctx ctx, int B, int R, int Hp, int Wp)
 {
@@ -231,6 +270,46 @@ me_status me_warp_features(me_ctx ctx, const void* z_ref, void* z_out, int32_t d
     hipError_t e = launch_warp(z_ref, z_out, dtype == ME_BF16, C, Hf, Wf, mv, bw, block / s, s,
                                reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "me_warp_features: launch");
+    return ME_OK;
+}
+
+me_status me_refine(me_ctx ctx, const me_frame* ref, const me_frame* cur, const me_params* params,
+                    const float* net_out, int16_t* mv, int32_t* sad, uint8_t* fallback, void* stream)
+{
+    if (!ctx) return fail(ME_E_INVAL, "me_refine: null context");
+    me_status s = check_pair(ref, cur);
+    if (s != ME_OK) return s;
+    if (!params || !net_out || !mv || !sad) return fail(ME_E_INVAL, "me_refine: null argument");
+    const me_params& p = *params;
+    if (!block_ok(p.block)) return fail(ME_E_UNSUPPORTED, "me_refine: block %d not in {8,16,32,64}", p.block);
+    if (p.radius < 0 || p.radius > 64) return fail(ME_E_INVAL, "me_refine: radius %d not in [0,64]", p.radius);
+    if (p.refine_radius < 0 || p.refine_radius > 8)
+        return fail(ME_E_INVAL, "me_refine: refine radius %d not in [0,8]", p.refine_radius);
+    if (!(p.sad_ratio >= 0.0f)) return fail(ME_E_INVAL, "me_refine: sad_ratio must be >= 0");
+    const float m = p.sad_median_per_sample > 0.0f ? p.sad_median_per_sample : ctx->median_per_sample;
+    if (!(m > 0.0f)) return fail(ME_E_STATE, "me_refine: no SAD median (params or loaded weights)");
+    const int Hp = cur->height / 2, Wp = cur->width / 2;
+    const int bh = (Hp + p.block - 1) / p.block, bw = (Wp + p.block - 1) / p.block;
+    const int nblk = bh * bw;
+    s = ensure_scratch(ctx, (size_t)nblk);
+    if (s != ME_OK) return s;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    uint8_t* fb = fallback ? fallback : ctx->fb;
+
+    hipError_t e = launch_decode(net_out, nblk, p.radius, ctx->pred, st);
+    if (e != hipSuccess) return hip_fail(e, "me_refine: decode");
+    SearchArgs a = make_args(ref, cur, p.block, p.refine_radius, p.radius, ctx->pred, mv, sad);
+    e = launch_sad_search(a, default_tiles(p.block, p.refine_radius), nblk, st);
+    if (e != hipSuccess) return hip_fail(e, "me_refine: refine search");
+    const double ratio_m = (double)p.sad_ratio * (double)m;
+    e = launch_fallback(net_out, sad, bh, bw, Hp, Wp, p.block, p.conf_logit_thresh, ratio_m, fb, ctx->list,
+                        ctx->count, st);
+    if (e != hipSuccess) return hip_fail(e, "me_refine: fallback");
+    SearchArgs f = make_args(ref, cur, p.block, p.radius, p.radius, nullptr, mv, sad);
+    f.list = ctx->list;
+    f.list_n = ctx->count;
+    e = launch_sad_search(f, tiles_for(ctx, p.block, p.radius, Hp, Wp), nblk, st);
+    if (e != hipSuccess) return hip_fail(e, "me_refine: fallback search");
     return ME_OK;
 }
 

@@ -60,6 +60,12 @@ hipError_t launch_sad_search(const SearchArgs& a, const TileCfg& cfg, int n_wg, 
 hipError_t launch_warp(const void* z, void* out, int bf16, int C, int Hf, int Wf, const int16_t* mv, int bw,
                        int cells, int s, hipStream_t stream);
 
+// Learned-proposal refine/fallback helpers (refine.hip).
+hipError_t launch_decode(const float* out, int nblk, int R, int16_t* pred, hipStream_t stream);
+hipError_t launch_fallback(const float* out, const int32_t* sad, int bh, int bw, int Hp, int Wp, int B,
+                           float conf_thresh, double ratio_m, uint8_t* fb, int32_t* list, int32_t* count,
+                           hipStream_t stream);
+
 hipError_t launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t stream);
 hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t stream);
 

@@ -62,11 +62,13 @@ _me_stage_search = _sig("me_stage_search", [_P, ctypes.POINTER(MeFrame), ctypes.
                                             _I32, _P, _P, _P])
 _me_warp_features = _sig("me_warp_features", [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _I32, _I32, _I32, _P])
 _me_batch_submit = _sig("me_batch_submit", [_P, ctypes.POINTER(MeJob), _I32, _P])
+_me_refine = _sig("me_refine", [_P, ctypes.POINTER(MeFrame), ctypes.POINTER(MeFrame), ctypes.POINTER(MeParams), _P, _P,
+                                _P, _P, _P])
 _me_status_string = _sig("me_status_string", [_I32], ctypes.c_char_p)
 _me_last_error = _sig("me_last_error", [], ctypes.c_char_p)
 
 EXPORTS = ["me_default_params", "me_ctx_create", "me_ctx_destroy", "me_estimate", "me_stage_search",
-           "me_warp_features", "me_batch_submit", "me_status_string", "me_last_error"]
+           "me_warp_features", "me_batch_submit", "me_refine", "me_status_string", "me_last_error"]
 
 
 class MeError(RuntimeError):
@@ -170,6 +172,28 @@ def stage_search(ref, cur, block, radius, pred=None, limit=None, mv=None, sad=No
                             None if pred is None else pred.data_ptr(), limit, mv.data_ptr(), sad.data_ptr(),
                             _stream_handle(stream)))
     return mv, sad
+
+
+def refine(ref, cur, net_out, ctx: Context, block=16, radius=32, refine_radius=2, conf_logit_thresh=0.0,
+           sad_ratio=1.5, sad_median_per_sample=0.0, mv=None, sad=None, fallback=None, stream=None):
+    """Learned-proposal refine + fallback given the network output [3, bh, bw] float32.
+    Returns (mv, sad, fallback)."""
+    H, W = cur.shape
+    bh, bw = block_grid(H, W, block)
+    if tuple(net_out.shape) != (3, bh, bw) or net_out.dtype != torch.float32 or not net_out.is_contiguous():
+        raise ValueError("net_out must be a contiguous float32 [3, %d, %d] tensor" % (bh, bw))
+    p = make_params(block, radius, ME_MODE_PROPOSAL, refine_radius, conf_logit_thresh, sad_ratio,
+                    sad_median_per_sample)
+    if mv is None:
+        mv = torch.empty((bh, bw, 2), dtype=torch.int16, device=cur.device)
+    if sad is None:
+        sad = torch.empty((bh, bw), dtype=torch.int32, device=cur.device)
+    if fallback is None:
+        fallback = torch.empty((bh, bw), dtype=torch.uint8, device=cur.device)
+    fr, fc = frame_of(ref), frame_of(cur)
+    _check(_me_refine(ctx.handle, ctypes.byref(fr), ctypes.byref(fc), ctypes.byref(p), net_out.data_ptr(),
+                      mv.data_ptr(), sad.data_ptr(), fallback.data_ptr(), _stream_handle(stream)))
+    return mv, sad, fallback
 
 
 def warp_features(z_ref: torch.Tensor, mv: torch.Tensor, block: int, frame_h: int, frame_w: int, out=None,

@@ -156,3 +156,14 @@ def test_batch_validation(me):
 
 def test_ctx_create_null_out(me):
     assert me._me_ctx_create(0, None) == 1
+
+
+def test_refine_validation(me):
+    f = _frame(me)
+    p = me.make_params(16, 8, me.ME_MODE_PROPOSAL)
+    args = lambda ctx, net: me._me_refine(ctx, ctypes.byref(f), ctypes.byref(f), ctypes.byref(p), net, FAKE, FAKE,
+                                          None, None)
+    assert args(None, FAKE) == 1                       # needs a context
+    assert args(ctypes.c_void_p(FAKE), 0) == 1         # null network output
+    p.refine_radius = 9
+    assert args(ctypes.c_void_p(FAKE), FAKE) == 1
