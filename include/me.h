@@ -172,6 +172,69 @@ me_status me_warp_features(me_ctx ctx, const void* z_ref, void* z_out, int32_t d
 me_status me_refine(me_ctx ctx, const me_frame* ref, const me_frame* cur, const me_params* params,
                     const float* net_out, int16_t* mv, int32_t* sad, uint8_t* fallback, void* stream);
 
+/*
+ * Proposal network (learned-proposal mode; this library's addition, see
+ * me_refine).  Input: for a frame pair of H x W Bayer samples (H, W divisible
+ * by 4), the 2x2 means of the four packed planes of the reference (channels
+ * 0-3) and current frame (4-7), normalised to (v - 2048) / 1024, bfloat16,
+ * channels last [H/4][W/4][8].  Four 3x3 convolutions, zero padding 1,
+ * strides 2, 2, 2, 1, channels 8 -> 32 -> 32 -> 32 -> 3, ReLU after the first
+ * three, bfloat16 weights and activations with float32 accumulation (MFMA);
+ * output float32 [3][bh][bw] per pair for 16x16 blocks: mvx, mvy (units of 8
+ * packed pixels) and a confidence logit.  Training loss: mean over blocks of
+ * the reverse Huber (BerHu, paper Sec. 3.3) of each vector component against
+ * full-search vector / 8 (threshold 1/8), plus the binary cross-entropy of
+ * the logit against "the full-search vector lies within refine_radius of the
+ * decoded proposal"; AdamW (beta 0.9/0.999, eps 1e-8, weight decay 0.01) as
+ * in the paper's training details (Sec. 4.1).
+ *
+ * Parameters: ME_CNN_NPARAMS float32 values, per layer W[out][in][3][3] then
+ * b[out], layers in order.  Activations between layers are bfloat16
+ * channels-last [n][h][w][32]; the output of layer 3 is float32
+ * [n][3][bh][bw].  Device buffers passed to these calls are 16-byte aligned.
+ */
+#define ME_CNN_NPARAMS 21699
+
+/* Set the master parameters (host array) and the median per-sample SAD used
+ * by the fallback test; resets the optimiser state.  Synchronous. */
+me_status me_cnn_set_params(me_ctx ctx, const float* params, int32_t count, float median_per_sample);
+/* Copy the master parameters (and median, if not NULL) to host memory.  Synchronous. */
+me_status me_cnn_get_params(me_ctx ctx, float* params, int32_t count, float* median_per_sample);
+/* Network input of one frame pair into x (device bfloat16 [H/4][W/4][8]). */
+me_status me_cnn_pool(me_ctx ctx, const me_frame* ref, const me_frame* cur, uint16_t* x, void* stream);
+/* Forward of n pooled inputs x ([n][Hq][Wq][8]) into out (device float32 [n][3][bh][bw]). */
+me_status me_cnn_forward(me_ctx ctx, const uint16_t* x, int32_t n, int32_t Hq, int32_t Wq, float* out, void* stream);
+/*
+ * One training step on n pooled inputs and their full-search vectors mv
+ * (device int16 [n][bh][bw][2]): forward, loss (mean over the n x bh x bw
+ * blocks), backward; with update != 0 an AdamW step with learning rate lr.
+ * grads (device float32 [ME_CNN_NPARAMS]) and loss (device float32 scalar)
+ * receive the gradient and loss when not NULL.  Weight gradients are reduced
+ * in a fixed order: the same inputs give bit-identical results.
+ */
+me_status me_cnn_train_step(me_ctx ctx, const uint16_t* x, const int16_t* mv, int32_t n, int32_t Hq, int32_t Wq,
+                            int32_t radius, int32_t refine_radius, float lr, int32_t update, float* grads,
+                            float* loss, void* stream);
+/* Checkpoint of the optimiser state (parameters, both moments, step count,
+ * median) in a host buffer of me_cnn_state_bytes() bytes.  Synchronous. */
+int64_t me_cnn_state_bytes(void);
+me_status me_cnn_save_state(me_ctx ctx, void* buf, int64_t bytes);
+me_status me_cnn_load_state(me_ctx ctx, const void* buf, int64_t bytes);
+/* Single stages, for checking each kernel on its own: layer `layer` (0..3)
+ * forward of a [n][H][W][cin] input; its backward given the layer input x and
+ * the gradient dz of its output ([n][Ho][Wo][coutp], coutp = 32, or 4 for
+ * layer 3 with channel 3 zero), writing the layer's slice of grads and, for
+ * layer > 0, the input gradient masked by the input's ReLU (x > 0) into dx;
+ * the loss of float32 outputs against labels (dz: bfloat16 [n][nblk][4],
+ * loss: float32 scalar; synchronous); an AdamW step with given gradients. */
+me_status me_cnn_layer_forward(me_ctx ctx, int32_t layer, const uint16_t* in, void* out, int32_t n, int32_t H,
+                               int32_t W, void* stream);
+me_status me_cnn_layer_backward(me_ctx ctx, int32_t layer, const uint16_t* x, const uint16_t* dz, uint16_t* dx,
+                                float* grads, int32_t n, int32_t H, int32_t W, void* stream);
+me_status me_cnn_loss(me_ctx ctx, const float* out, const int16_t* mv, int32_t n, int32_t nblk, int32_t radius,
+                      int32_t refine_radius, uint16_t* dz, float* loss, void* stream);
+me_status me_cnn_adamw(me_ctx ctx, const float* grads, float lr, void* stream);
+
 /* One frame pair of a batch (me_batch_submit). */
 typedef struct {
     me_frame ref;

@@ -5,19 +5,17 @@
 #include <stdio.h>
 #include <string.h>
 
-#include <map>
-#include <mutex>
 #include <new>
-#include <tuple>
 
-#include "../../include/me.h"
-#include "internal.h"
+#include "ctx.h"
 
 using namespace me;
 
 namespace {
-
 thread_local char g_err[512] = "";
+}  // namespace
+
+namespace me {
 
 me_status fail(me_status s, const char* fmt, ...)
 {
@@ -83,33 +81,18 @@ SearchArgs make_args(const me_frame* ref, const me_frame* cur, int B, int R, int
     return a;
 }
 
-}  // namespace
+}  // namespace me
 
-struct me_ctx_s {
-    int device = 0;
-    std::mutex mu;
-    // launch shapes picked by the tuner, keyed by (B, R, Hp, Wp)
-    std::map<std::tuple<int, int, int, int>, TileCfg> tuned;
-    // proposal-mode scratch, grown on demand: decoded proposals, fallback
-    // flags, the compacted fallback list and its device count
-    int16_t* pred = nullptr;
-    uint8_t* fb = nullptr;
-    int32_t* list = nullptr;
-    int32_t* count = nullptr;
-    size_t cap_blocks = 0;
-    // SAD per sample of the exhaustive best match, median over training data
-    float median_per_sample = 0.0f;
+me_ctx_s::~me_ctx_s()
+{
+    (void)hipFree(pred);
+    (void)hipFree(fb);
+    (void)hipFree(list);
+    (void)hipFree(count);
+    cnn.release();
+}
 
-    ~me_ctx_s()
-    {
-        (void)hipFree(pred);
-        (void)hipFree(fb);
-        (void)hipFree(list);
-        (void)hipFree(count);
-    }
-};
-
-namespace {
+namespace me {
 
 me_status ensure_scratch(me_ctx ctx, size_t nblk)
 {
@@ -143,7 +126,46 @@ TileCfg tiles_for(me_ctx ctx, int B, int R, int Hp, int Wp)
     return default_tiles(B, R);
 }
 
-}  // namespace
+me_status refine_impl(me_ctx ctx, const me_frame* ref, const me_frame* cur, const me_params& p, const float* net_out,
+                      int16_t* mv, int32_t* sad, uint8_t* fallback, hipStream_t st)
+{
+    const float m = p.sad_median_per_sample > 0.0f ? p.sad_median_per_sample : ctx->median_per_sample;
+    if (!(m > 0.0f)) return fail(ME_E_STATE, "refine: no SAD median (params or loaded weights)");
+    const int Hp = cur->height / 2, Wp = cur->width / 2;
+    const int bh = (Hp + p.block - 1) / p.block, bw = (Wp + p.block - 1) / p.block;
+    const int nblk = bh * bw;
+    me_status s = ensure_scratch(ctx, (size_t)nblk);
+    if (s != ME_OK) return s;
+    uint8_t* fb = fallback ? fallback : ctx->fb;
+
+    hipError_t e = launch_decode(net_out, nblk, p.radius, ctx->pred, st);
+    if (e != hipSuccess) return hip_fail(e, "refine: decode");
+    SearchArgs a = make_args(ref, cur, p.block, p.refine_radius, p.radius, ctx->pred, mv, sad);
+    e = launch_sad_search(a, default_tiles(p.block, p.refine_radius), nblk, st);
+    if (e != hipSuccess) return hip_fail(e, "refine: refine search");
+    const double ratio_m = (double)p.sad_ratio * (double)m;
+    e = launch_fallback(net_out, sad, bh, bw, Hp, Wp, p.block, p.conf_logit_thresh, ratio_m, fb, ctx->list,
+                        ctx->count, st);
+    if (e != hipSuccess) return hip_fail(e, "refine: fallback");
+    SearchArgs f = make_args(ref, cur, p.block, p.radius, p.radius, nullptr, mv, sad);
+    f.list = ctx->list;
+    f.list_n = ctx->count;
+    e = launch_sad_search(f, tiles_for(ctx, p.block, p.radius, Hp, Wp), nblk, st);
+    if (e != hipSuccess) return hip_fail(e, "refine: fallback search");
+    return ME_OK;
+}
+
+static me_status check_refine_params(const me_params& p)
+{
+    if (!block_ok(p.block)) return fail(ME_E_UNSUPPORTED, "block %d not in {8,16,32,64}", p.block);
+    if (p.radius < 0 || p.radius > 64) return fail(ME_E_INVAL, "radius %d not in [0,64]", p.radius);
+    if (p.refine_radius < 0 || p.refine_radius > 8)
+        return fail(ME_E_INVAL, "refine radius %d not in [0,8]", p.refine_radius);
+    if (!(p.sad_ratio >= 0.0f)) return fail(ME_E_INVAL, "sad_ratio must be >= 0");
+    return ME_OK;
+}
+
+}  // namespace me
 
 extern "C" {
 
@@ -211,9 +233,18 @@ me_status me_estimate(me_ctx ctx, const me_frame* ref, const me_frame* cur, cons
     if (p.step != 1) return fail(ME_E_UNSUPPORTED, "me_estimate: step %d (only 1 is supported)", p.step);
     if (p.mode != ME_MODE_EXHAUSTIVE && p.mode != ME_MODE_PROPOSAL)
         return fail(ME_E_INVAL, "me_estimate: unknown mode %d", p.mode);
-    if (p.mode == ME_MODE_PROPOSAL) return fail(ME_E_STATE, "me_estimate: proposal mode needs loaded weights");
-
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (p.mode == ME_MODE_PROPOSAL) {
+        if (!ctx || !ctx->cnn.loaded) return fail(ME_E_STATE, "me_estimate: proposal mode needs loaded weights");
+        s = check_refine_params(p);
+        if (s != ME_OK) return s;
+        if (p.block != 16 || (cur->height % 4) || (cur->width % 4))
+            return fail(ME_E_UNSUPPORTED, "me_estimate: proposal mode needs B=16 and frame sides divisible by 4");
+        s = cnn_propose(ctx, ref, cur, st);
+        if (s != ME_OK) return s;
+        return refine_impl(ctx, ref, cur, p, ctx->cnn.out, mv, sad, fallback, st);
+    }
+
     SearchArgs a = make_args(ref, cur, p.block, p.radius, p.radius, nullptr, mv, sad);
     const TileCfg cfg = tiles_for(ctx, p.block, p.radius, a.Hp, a.Wp);
     hipError_t e = launch_sad_search(a, cfg, a.bh * a.bw, st);
@@ -280,37 +311,9 @@ me_status me_refine(me_ctx ctx, const me_frame* ref, const me_frame* cur, const 
     me_status s = check_pair(ref, cur);
     if (s != ME_OK) return s;
     if (!params || !net_out || !mv || !sad) return fail(ME_E_INVAL, "me_refine: null argument");
-    const me_params& p = *params;
-    if (!block_ok(p.block)) return fail(ME_E_UNSUPPORTED, "me_refine: block %d not in {8,16,32,64}", p.block);
-    if (p.radius < 0 || p.radius > 64) return fail(ME_E_INVAL, "me_refine: radius %d not in [0,64]", p.radius);
-    if (p.refine_radius < 0 || p.refine_radius > 8)
-        return fail(ME_E_INVAL, "me_refine: refine radius %d not in [0,8]", p.refine_radius);
-    if (!(p.sad_ratio >= 0.0f)) return fail(ME_E_INVAL, "me_refine: sad_ratio must be >= 0");
-    const float m = p.sad_median_per_sample > 0.0f ? p.sad_median_per_sample : ctx->median_per_sample;
-    if (!(m > 0.0f)) return fail(ME_E_STATE, "me_refine: no SAD median (params or loaded weights)");
-    const int Hp = cur->height / 2, Wp = cur->width / 2;
-    const int bh = (Hp + p.block - 1) / p.block, bw = (Wp + p.block - 1) / p.block;
-    const int nblk = bh * bw;
-    s = ensure_scratch(ctx, (size_t)nblk);
+    s = check_refine_params(*params);
     if (s != ME_OK) return s;
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    uint8_t* fb = fallback ? fallback : ctx->fb;
-
-    hipError_t e = launch_decode(net_out, nblk, p.radius, ctx->pred, st);
-    if (e != hipSuccess) return hip_fail(e, "me_refine: decode");
-    SearchArgs a = make_args(ref, cur, p.block, p.refine_radius, p.radius, ctx->pred, mv, sad);
-    e = launch_sad_search(a, default_tiles(p.block, p.refine_radius), nblk, st);
-    if (e != hipSuccess) return hip_fail(e, "me_refine: refine search");
-    const double ratio_m = (double)p.sad_ratio * (double)m;
-    e = launch_fallback(net_out, sad, bh, bw, Hp, Wp, p.block, p.conf_logit_thresh, ratio_m, fb, ctx->list,
-                        ctx->count, st);
-    if (e != hipSuccess) return hip_fail(e, "me_refine: fallback");
-    SearchArgs f = make_args(ref, cur, p.block, p.radius, p.radius, nullptr, mv, sad);
-    f.list = ctx->list;
-    f.list_n = ctx->count;
-    e = launch_sad_search(f, tiles_for(ctx, p.block, p.radius, Hp, Wp), nblk, st);
-    if (e != hipSuccess) return hip_fail(e, "me_refine: fallback search");
-    return ME_OK;
+    return refine_impl(ctx, ref, cur, *params, net_out, mv, sad, fallback, reinterpret_cast<hipStream_t>(stream));
 }
 
 me_status me_batch_submit(me_ctx ctx, const me_job* jobs, int32_t n, void* stream)

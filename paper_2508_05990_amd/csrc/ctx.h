@@ -1,0 +1,80 @@
+// Library context and shared host-side helpers of the C ABI (not public).
+#pragma once
+
+#include <stdint.h>
+
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "../../include/me.h"
+#include "internal.h"
+
+namespace me {
+
+me_status fail(me_status s, const char* fmt, ...);
+me_status hip_fail(hipError_t e, const char* what);
+me_status check_frame(const me_frame* f, const char* name);
+me_status check_pair(const me_frame* ref, const me_frame* cur);
+bool block_ok(int B);
+SearchArgs make_args(const me_frame* ref, const me_frame* cur, int B, int R, int limit, const int16_t* pred,
+                     int16_t* mv, int32_t* sad);
+
+// Proposal-network state: float32 master parameters, AdamW moments, the
+// bfloat16 operand packings, and activation/gradient buffers sized for the
+// largest batch seen so far.
+struct CnnState {
+    bool loaded = false;
+    float* params = nullptr;
+    float* m = nullptr;
+    float* v = nullptr;
+    float* grads = nullptr;
+    uint16_t* wf = nullptr;
+    uint16_t* wb = nullptr;
+    int64_t step = 0;
+    int cap_n = 0, cap_hq = 0, cap_wq = 0;
+    uint16_t* a0 = nullptr;   // pooled input of the proposal mode (one pair)
+    uint16_t* a1 = nullptr;
+    uint16_t* a2 = nullptr;
+    uint16_t* a3 = nullptr;
+    float* out = nullptr;
+    uint16_t* dz4 = nullptr;
+    uint16_t* d3 = nullptr;
+    uint16_t* d2 = nullptr;
+    uint16_t* d1 = nullptr;
+    float* bl = nullptr;
+    float* partial = nullptr;
+    size_t partial_cap = 0;   // floats
+    void release();
+};
+
+}  // namespace me
+
+struct me_ctx_s {
+    int device = 0;
+    std::mutex mu;
+    // launch shapes picked by the tuner, keyed by (B, R, Hp, Wp)
+    std::map<std::tuple<int, int, int, int>, me::TileCfg> tuned;
+    // proposal-mode scratch, grown on demand: decoded proposals, fallback
+    // flags, the compacted fallback list and its device count
+    int16_t* pred = nullptr;
+    uint8_t* fb = nullptr;
+    int32_t* list = nullptr;
+    int32_t* count = nullptr;
+    size_t cap_blocks = 0;
+    // SAD per sample of the full-search best match, median over training data
+    float median_per_sample = 0.0f;
+    me::CnnState cnn;
+
+    ~me_ctx_s();
+};
+
+namespace me {
+me_status ensure_scratch(me_ctx ctx, size_t nblk);
+TileCfg tiles_for(me_ctx ctx, int B, int R, int Hp, int Wp);
+// Refine + fallback on a network output already in device memory.
+me_status refine_impl(me_ctx ctx, const me_frame* ref, const me_frame* cur, const me_params& p, const float* net_out,
+                      int16_t* mv, int32_t* sad, uint8_t* fallback, hipStream_t st);
+// Pool + forward of one pair into ctx->cnn.out (proposal mode).
+me_status cnn_propose(me_ctx ctx, const me_frame* ref, const me_frame* cur, hipStream_t st);
+}  // namespace me

@@ -66,6 +66,27 @@ hipError_t launch_fallback(const float* out, const int32_t* sad, int bh, int bw,
                            float conf_thresh, double ratio_m, uint8_t* fb, int32_t* list, int32_t* count,
                            hipStream_t stream);
 
+// Proposal network (cnn.hip).  Layer l = 0..3: (cin, cout, stride) =
+// (8,32,2), (32,32,2), (32,32,2), (32,3,1).
+constexpr int kCnnParams = 21699;
+int cnn_fwd_packed_size(int l);
+int cnn_bwd_packed_size(int l);
+int cnn_wgrad_groups(int n, int Ho, int Wo);
+size_t cnn_wgrad_partial_floats(int l, int nwg);
+hipError_t launch_pool(const uint16_t* ref, int64_t ref_pitch, const uint16_t* cur, int64_t cur_pitch, int Hq, int Wq,
+                       uint16_t* out, hipStream_t st);
+hipError_t launch_pack(const float* w, uint16_t* fwd, uint16_t* bwd, hipStream_t st);
+hipError_t launch_conv_fwd(int l, const uint16_t* in, const uint16_t* wp, const float* bias, void* out, int n, int H,
+                           int W, int Ho, int Wo, hipStream_t st);
+hipError_t launch_loss(const float* out, const int16_t* mv, int n, int nblk, int R, int rr, uint16_t* dz, float* bl,
+                       float* loss, hipStream_t st);
+hipError_t launch_conv_dgrad(int l, const uint16_t* dz, const uint16_t* wb, const uint16_t* aprev, uint16_t* dprev,
+                             int n, int H, int W, int Ho, int Wo, hipStream_t st);
+hipError_t launch_conv_wgrad(int l, const uint16_t* x, const uint16_t* dz, float* partial, float* grads, int n, int H,
+                             int W, int Ho, int Wo, hipStream_t st);
+hipError_t launch_adamw(float* w, const float* g, float* m, float* v, int np, float lr, float b1, float b2, float eps,
+                        float wd, float c1, float c2, hipStream_t st);
+
 hipError_t launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t stream);
 hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t stream);
 

@@ -64,11 +64,28 @@ _me_warp_features = _sig("me_warp_features", [_P, _P, _P, _I32, _I32, _I32, _I32
 _me_batch_submit = _sig("me_batch_submit", [_P, ctypes.POINTER(MeJob), _I32, _P])
 _me_refine = _sig("me_refine", [_P, ctypes.POINTER(MeFrame), ctypes.POINTER(MeFrame), ctypes.POINTER(MeParams), _P, _P,
                                 _P, _P, _P])
+_F = ctypes.c_float
+_me_cnn_set_params = _sig("me_cnn_set_params", [_P, _P, _I32, _F])
+_me_cnn_get_params = _sig("me_cnn_get_params", [_P, _P, _I32, _P])
+_me_cnn_pool = _sig("me_cnn_pool", [_P, ctypes.POINTER(MeFrame), ctypes.POINTER(MeFrame), _P, _P])
+_me_cnn_forward = _sig("me_cnn_forward", [_P, _P, _I32, _I32, _I32, _P, _P])
+_me_cnn_train_step = _sig("me_cnn_train_step", [_P, _P, _P, _I32, _I32, _I32, _I32, _I32, _F, _I32, _P, _P, _P])
+_me_cnn_state_bytes = _sig("me_cnn_state_bytes", [], ctypes.c_int64)
+_me_cnn_save_state = _sig("me_cnn_save_state", [_P, _P, ctypes.c_int64])
+_me_cnn_load_state = _sig("me_cnn_load_state", [_P, _P, ctypes.c_int64])
+_me_cnn_layer_forward = _sig("me_cnn_layer_forward", [_P, _I32, _P, _P, _I32, _I32, _I32, _P])
+_me_cnn_layer_backward = _sig("me_cnn_layer_backward", [_P, _I32, _P, _P, _P, _P, _I32, _I32, _I32, _P])
+_me_cnn_loss = _sig("me_cnn_loss", [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P])
+_me_cnn_adamw = _sig("me_cnn_adamw", [_P, _P, _F, _P])
 _me_status_string = _sig("me_status_string", [_I32], ctypes.c_char_p)
 _me_last_error = _sig("me_last_error", [], ctypes.c_char_p)
 
 EXPORTS = ["me_default_params", "me_ctx_create", "me_ctx_destroy", "me_estimate", "me_stage_search",
-           "me_warp_features", "me_batch_submit", "me_refine", "me_status_string", "me_last_error"]
+           "me_warp_features", "me_batch_submit", "me_refine", "me_status_string", "me_last_error",
+           "me_cnn_set_params", "me_cnn_get_params", "me_cnn_pool", "me_cnn_forward", "me_cnn_train_step",
+           "me_cnn_state_bytes", "me_cnn_save_state", "me_cnn_load_state", "me_cnn_layer_forward",
+           "me_cnn_layer_backward", "me_cnn_loss", "me_cnn_adamw"]
+ME_CNN_NPARAMS = 21699
 
 
 class MeError(RuntimeError):
@@ -225,3 +242,91 @@ def batch_submit(ctx: Context, jobs, stream=None):
         arr[k].mv = mv.data_ptr()
         arr[k].sad = sad.data_ptr()
     _check(_me_batch_submit(ctx.handle, arr, len(jobs), _stream_handle(stream)))
+
+
+# --- proposal network ---------------------------------------------------------
+
+def _p(t):
+    return None if t is None else t.data_ptr()
+
+
+def cnn_set_params(ctx: Context, params, median_per_sample: float):
+    import numpy as np
+
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    _check(_me_cnn_set_params(ctx.handle, a.ctypes.data, a.size, median_per_sample))
+
+
+def cnn_get_params(ctx: Context):
+    import numpy as np
+
+    a = np.empty(ME_CNN_NPARAMS, np.float32)
+    m = ctypes.c_float()
+    _check(_me_cnn_get_params(ctx.handle, a.ctypes.data, a.size, ctypes.addressof(m)))
+    return a, m.value
+
+
+def cnn_pool(ctx, ref, cur, x=None, stream=None):
+    """Network input [H/4, W/4, 8] bfloat16 of one frame pair."""
+    H, W = cur.shape
+    if x is None:
+        x = torch.empty((H // 4, W // 4, 8), dtype=torch.bfloat16, device=cur.device)
+    fr, fc = frame_of(ref), frame_of(cur)
+    _check(_me_cnn_pool(_ctx_handle(ctx), ctypes.byref(fr), ctypes.byref(fc), x.data_ptr(), _stream_handle(stream)))
+    return x
+
+
+def _out_grid(Hq, Wq):
+    for _ in range(3):
+        Hq, Wq = (Hq + 1) // 2, (Wq + 1) // 2
+    return Hq, Wq
+
+
+def cnn_forward(ctx, x, out=None, stream=None):
+    """x: [n, Hq, Wq, 8] bfloat16 -> [n, 3, bh, bw] float32."""
+    n, Hq, Wq, _ = x.shape
+    bh, bw = _out_grid(Hq, Wq)
+    if out is None:
+        out = torch.empty((n, 3, bh, bw), dtype=torch.float32, device=x.device)
+    _check(_me_cnn_forward(ctx.handle, x.data_ptr(), n, Hq, Wq, out.data_ptr(), _stream_handle(stream)))
+    return out
+
+
+def cnn_train_step(ctx, x, mv, radius=32, refine_radius=2, lr=1e-4, update=True, grads=None, loss=None,
+                   stream=None):
+    n, Hq, Wq, _ = x.shape
+    _check(_me_cnn_train_step(ctx.handle, x.data_ptr(), mv.data_ptr(), n, Hq, Wq, radius, refine_radius, lr,
+                              1 if update else 0, _p(grads), _p(loss), _stream_handle(stream)))
+
+
+def cnn_save_state(ctx) -> bytes:
+    nb = _me_cnn_state_bytes()
+    buf = ctypes.create_string_buffer(nb)
+    _check(_me_cnn_save_state(ctx.handle, ctypes.addressof(buf), nb))
+    return buf.raw
+
+
+def cnn_load_state(ctx, blob: bytes):
+    buf = ctypes.create_string_buffer(blob, len(blob))
+    _check(_me_cnn_load_state(ctx.handle, ctypes.addressof(buf), len(blob)))
+
+
+def cnn_layer_forward(ctx, layer, inp, out, stream=None):
+    n, H, W, _ = inp.shape
+    _check(_me_cnn_layer_forward(ctx.handle, layer, inp.data_ptr(), out.data_ptr(), n, H, W, _stream_handle(stream)))
+
+
+def cnn_layer_backward(ctx, layer, x, dz, dx, grads, stream=None):
+    n, H, W, _ = x.shape
+    _check(_me_cnn_layer_backward(ctx.handle, layer, x.data_ptr(), dz.data_ptr(), _p(dx), grads.data_ptr(), n, H, W,
+                                  _stream_handle(stream)))
+
+
+def cnn_loss(ctx, out, mv, radius, refine_radius, dz, loss, stream=None):
+    n, _, bh, bw = out.shape
+    _check(_me_cnn_loss(ctx.handle, out.data_ptr(), mv.data_ptr(), n, bh * bw, radius, refine_radius, dz.data_ptr(),
+                        loss.data_ptr(), _stream_handle(stream)))
+
+
+def cnn_adamw(ctx, grads, lr, stream=None):
+    _check(_me_cnn_adamw(ctx.handle, grads.data_ptr(), lr, _stream_handle(stream)))
