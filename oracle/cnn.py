@@ -189,28 +189,30 @@ def labels(out, mv_exh, R, refine_radius):
     return (e <= refine_radius).astype(np.float64)
 
 
-def loss_and_grad(out, mv_exh, R, refine_radius=2, y=None):
-    """Mean over blocks of BerHu(o_x - t_x) + BerHu(o_y - t_y), t = full-search
-    vector / 8, plus mean BCE of the logit against the refine-success label.
+def loss_and_grad(out, mv_exh, R, refine_radius=2, y=None, weight=None):
+    """Mean over blocks of w * (BerHu(o_x - t_x) + BerHu(o_y - t_y)), t =
+    full-search vector / 8, plus mean BCE of the logit against the
+    refine-success label; w = per-block weight of the vector term (default 1).
     Returns (loss, dL/d(out) [3, bh, bw])."""
     out = np.asarray(out, dtype=np.float64)
     mv = np.asarray(mv_exh, dtype=np.float64)
     n = out.shape[1] * out.shape[2]
+    w = np.ones(out.shape[1:]) if weight is None else np.asarray(weight, dtype=np.float64)
     if y is None:
         y = labels(out, mv, R, refine_radius)
     ex = out[0] - mv[..., 0] / 8.0
     ey = out[1] - mv[..., 1] / 8.0
-    loss = (berhu(ex).sum() + berhu(ey).sum() + bce_logits(out[2], y).sum()) / n
-    g = np.stack([berhu_grad(ex), berhu_grad(ey), sigmoid(out[2]) - y]) / n
+    loss = ((w * (berhu(ex) + berhu(ey))).sum() + bce_logits(out[2], y).sum()) / n
+    g = np.stack([w * berhu_grad(ex), w * berhu_grad(ey), sigmoid(out[2]) - y]) / n
     return loss, g
 
 
-def batch_loss_and_grads(params, xs, mvs, R, refine_radius=2, rnd=bf16_round):
+def batch_loss_and_grads(params, xs, mvs, R, refine_radius=2, rnd=bf16_round, weights=None):
     """Mean loss over a batch of pairs and the gradient of that mean."""
     tot, g = 0.0, np.zeros(NPARAMS)
-    for x, mv in zip(xs, mvs):
+    for k, (x, mv) in enumerate(zip(xs, mvs)):
         out, acts, pres = forward(params, x, rnd)
-        L, dout = loss_and_grad(out, mv, R, refine_radius)
+        L, dout = loss_and_grad(out, mv, R, refine_radius, weight=None if weights is None else weights[k])
         tot += L
         g += backward(params, acts, pres, dout, rnd)
     return tot / len(xs), g / len(xs)

@@ -122,6 +122,30 @@ def test_network_gradient_finite_differences():
         assert abs(fd - g[i]) <= 1e-5 * max(1.0, abs(fd)), (i, fd, g[i])
 
 
+def test_weighted_loss():
+    """Per-block weight of the vector term: zero weights leave the mean BCE
+    alone; the gradient matches central differences of the weighted loss."""
+    rng = np.random.default_rng(9)
+    out = rng.normal(0, 1, (3, 4, 5))
+    mv = rng.integers(-12, 13, (4, 5, 2))
+    y = cnn.labels(out, mv, 16, 2)
+    L0, g0 = cnn.loss_and_grad(out, mv, 16, 2, y=y, weight=np.zeros((4, 5)))
+    assert L0 == pytest.approx(cnn.bce_logits(out[2], y).mean(), rel=1e-12)
+    assert not g0[:2].any()
+    w = rng.choice([0.0, 0.5, 1.0, 2.0], (4, 5))
+    L1, _ = cnn.loss_and_grad(out, mv, 16, 2, y=y)
+    Lw, gw = cnn.loss_and_grad(out, mv, 16, 2, y=y, weight=w)
+    ones, _ = cnn.loss_and_grad(out, mv, 16, 2, y=y, weight=np.ones((4, 5)))
+    assert ones == L1
+    h = 1e-6
+    for idx in [(0, 1, 2), (1, 3, 4), (0, 0, 0), (2, 2, 1)]:
+        op, om = out.copy(), out.copy()
+        op[idx] += h
+        om[idx] -= h
+        fd = (cnn.loss_and_grad(op, mv, 16, 2, y=y, weight=w)[0] - cnn.loss_and_grad(om, mv, 16, 2, y=y, weight=w)[0]) / (2 * h)
+        assert gw[idx] == pytest.approx(fd, rel=1e-5, abs=1e-9)
+
+
 def test_berhu_and_bce():
     c = cnn.BERHU_C
     assert cnn.berhu(c) == pytest.approx(c) and cnn.berhu(c + 1e-12) == pytest.approx(c)   # continuous at c
