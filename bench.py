@@ -75,6 +75,159 @@ def cpu_baseline(frames, feats, B, R, budget_s):
                       "[%d,%d,%d], %.1f s" % (n, B, R, *feats.shape, el)}
 
 
+def proposal_leg(me, ctx, frames, mvs_exh, z, outs, B, R, H, W, args):
+    """Learned-proposal mode on the same sequence (same GPU, same warp):
+    frames/s, MV-error rate against full search (Euclidean error > 1 packed
+    pixel) and fallback rate."""
+    import numpy as np
+    import torch
+
+    from paper_2508_05990_amd import train
+
+    path = args.weights or train.DEFAULT_WEIGHTS
+    if not os.path.exists(path):
+        return {"skipped": "no weights at %s" % path}
+    params, median = train.load_weights(path)
+    me.cnn_set_params(ctx, params, median)
+    p = me.make_params(B, R, me.ME_MODE_PROPOSAL, 2, 0.0, 1.5, 0.0)
+    npairs = len(frames) - 1
+    bh, bw = mvs_exh[0].shape[:2]
+    mv = [torch.empty((bh, bw, 2), dtype=torch.int16, device="cuda") for _ in range(npairs)]
+    sad = [torch.empty((bh, bw), dtype=torch.int32, device="cuda") for _ in range(npairs)]
+    fb = [torch.empty((bh, bw), dtype=torch.uint8, device="cuda") for _ in range(npairs)]
+
+    def step():
+        for t in range(npairs):
+            me.estimate(frames[t], frames[t + 1], mv=mv[t], sad=sad[t], fallback=fb[t], params=p, ctx=ctx)
+            me.warp_features(z, mv[t], B, H, W, out=outs[t & 1], ctx=ctx)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    err = fall = 0
+    for t in range(npairs):
+        d = (mv[t].int() - mvs_exh[t].int()).float()
+        err += int(((d[..., 0] ** 2 + d[..., 1] ** 2) > 1.0).sum().item())
+        fall += int(fb[t].sum().item())
+    nb = npairs * bh * bw
+    return {"value": round(npairs * args.steps / wall, 2), "unit": "frames/s", "mv_err_rate": err / nb,
+            "fallback_rate": fall / nb, "refine_radius": 2, "weights": os.path.relpath(path, ROOT),
+            "ms_per_step": round(wall * 1e3 / args.steps, 4)}
+
+
+def batched_leg(me, ctx, args):
+    """24 independent streams of 8 frames (640x480 to 3840x2160, (B, R) in
+    {8, 16} x {16, 32}): 168 pairs as one graph-captured persistent launch
+    versus one launch per pair, with identical results required."""
+    import numpy as np
+    import torch
+
+    from paper_2508_05990_amd import synth
+
+    jobs, singles, ops = [], [], 0
+    for B, R, seq in synth.stream_sequences(2):
+        fr = [torch.from_numpy(f).cuda() for f in seq.frames]
+        H, W = seq.shape
+        bh, bw = me.block_grid(H, W, B)
+        p = me.make_params(B, R)
+        for t in range(1, len(fr)):
+            mk = lambda: (torch.empty((bh, bw, 2), dtype=torch.int16, device="cuda"),
+                          torch.empty((bh, bw), dtype=torch.int32, device="cuda"))
+            mv, sad = mk()
+            jobs.append((fr[t - 1], fr[t], B, R, mv, sad))
+            singles.append((fr[t - 1], fr[t], p) + mk())
+            ops += sad_ops(H // 2, W // 2, B, R)
+    arr = me.make_jobs(jobs)
+    steps = max(2, args.steps // 4)
+
+    def batched():
+        me.batch_submit(ctx, arr)
+
+    def per_pair():
+        for ref, cur, p, mv, sad in singles:
+            me.estimate(ref, cur, mv=mv, sad=sad, params=p, ctx=ctx)
+
+    out = {}
+    for name, fn in (("batched", batched), ("per_pair_launches", per_pair)):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        a.record()
+        for _ in range(steps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        out[name + "_ms"] = round(a.elapsed_time(b) / steps, 4)
+        out[name + "_wall_ms"] = round(wall * 1e3, 4)
+    same = all(torch.equal(j[4], s[3]) and torch.equal(j[5], s[4]) for j, s in zip(jobs, singles))
+    tops = ops / (out["batched_ms"] * 1e-3) / 1e12
+    out.update({"workload": "24 streams x 8 frames, 168 pairs, mixed sizes and (B, R)", "pairs": len(jobs),
+                "sad_ops": ops, "frames_per_s": round(len(jobs) / (out["batched_ms"] * 1e-3), 1),
+                "speedup_vs_per_pair": round(out["per_pair_launches_ms"] / out["batched_ms"], 3),
+                "achieved_tops": round(tops, 3), "frac": round(tops / PEAK_SAD_TOPS, 4),
+                "identical_to_per_pair": bool(same), "steps": steps})
+    return out
+
+
+def uhd_leg(me, ctx, args):
+    """3840x2160 sequence, full search B=16 R=64 and bfloat16 warp of [256, 270, 480]."""
+    import numpy as np
+    import torch
+
+    from paper_2508_05990_amd import synth
+
+    B, R = 16, 64
+    seq = synth.uhd_sequence(4, n_frames=args.uhd_frames)
+    H, W = seq.shape
+    fr = [torch.from_numpy(f).cuda() for f in seq.frames]
+    z = torch.from_numpy(synth.features(12, 256, 270, 480)).cuda().to(torch.bfloat16)
+    outz = torch.empty_like(z)
+    bh, bw = me.block_grid(H, W, B)
+    mv = torch.empty((bh, bw, 2), dtype=torch.int16, device="cuda")
+    sad = torch.empty((bh, bw), dtype=torch.int32, device="cuda")
+    p = me.make_params(B, R)
+    npairs = len(fr) - 1
+    steps = max(2, args.steps // 4)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps * npairs)]
+
+    def step(k):
+        for t in range(npairs):
+            e = ev[k * npairs + t] if k >= 0 else None
+            if e:
+                e[0].record()
+            me.estimate(fr[t], fr[t + 1], mv=mv, sad=sad, params=p, ctx=ctx)
+            if e:
+                e[1].record()
+            me.warp_features(z, mv, B, H, W, out=outz, ctx=ctx)
+            if e:
+                e[2].record()
+
+    step(-1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(k)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    me_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    warp_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    ops = sad_ops(H // 2, W // 2, B, R)
+    tops = ops / (me_ms * 1e-3) / 1e12
+    wb = 2 * z.numel() * z.element_size()
+    return {"workload": "3840x2160 RGGB sequence, %d frames, full search B=16 R=64, bf16 warp [256,270,480]"
+                        % len(fr), "value": round(npairs * steps / wall, 2), "unit": "frames/s",
+            "me_ms_per_pair": round(me_ms, 4), "sad_ops_per_pair": ops, "achieved_tops": round(tops, 3),
+            "frac": round(tops / PEAK_SAD_TOPS, 4), "warp_us_per_pair": round(warp_ms * 1e3, 2),
+            "warp_hbm_frac": round(wb / (warp_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4), "steps": steps}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +235,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline budget (0 = skip)")
     ap.add_argument("--warp-dtype", choices=["f32", "bf16"], default="f32")
+    ap.add_argument("--no-proposal", action="store_true", help="skip the learned-proposal measurement")
+    ap.add_argument("--weights", default=None, help="proposal-network weights (default: the packaged file)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 24-stream batched measurement")
+    ap.add_argument("--uhd-frames", type=int, default=16, help="frames of the 4K sequence (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -181,6 +338,12 @@ def main():
         "warp_gbs": round(warp_bytes / (warp_avg * 1e-3) / 1e9, 1),
         "warp_hbm_frac": round(warp_bytes / (warp_avg * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
     }
+    if not args.no_proposal:
+        res["proposal"] = proposal_leg(me, ctx, frames, mvs, z, outs, B, R, H, W, args)
+    if not args.no_batched:
+        res["batched_streams"] = batched_leg(me, ctx, args)
+    if args.uhd_frames > 1:
+        res["uhd"] = uhd_leg(me, ctx, args)
     if args.cpu_seconds > 0:
         res["cpu_baseline"] = cpu_baseline(seq.frames, feats, B, R, args.cpu_seconds)
     ctx.close()

@@ -207,14 +207,18 @@ me_status me_cnn_forward(me_ctx ctx, const uint16_t* x, int32_t n, int32_t Hq, i
 /*
  * One training step on n pooled inputs and their full-search vectors mv
  * (device int16 [n][bh][bw][2]): forward, loss (mean over the n x bh x bw
- * blocks), backward; with update != 0 an AdamW step with learning rate lr.
- * grads (device float32 [ME_CNN_NPARAMS]) and loss (device float32 scalar)
- * receive the gradient and loss when not NULL.  Weight gradients are reduced
- * in a fixed order: the same inputs give bit-identical results.
+ * blocks of w x (BerHu of the two vector components) + BCE of the confidence
+ * logit, Sec. 3.3 loss family), backward; with update != 0 an AdamW step with
+ * learning rate lr.  weight (device float32 [n][bh][bw], NULL = all 1) is the
+ * per-block weight w of the vector term, e.g. 0 for blocks whose full-search
+ * match is too poor for a proposal ever to be accepted.  grads (device
+ * float32 [ME_CNN_NPARAMS]) and loss (device float32 scalar) receive the
+ * gradient and loss when not NULL.  Weight gradients are reduced in a fixed
+ * order: the same inputs give bit-identical results.
  */
-me_status me_cnn_train_step(me_ctx ctx, const uint16_t* x, const int16_t* mv, int32_t n, int32_t Hq, int32_t Wq,
-                            int32_t radius, int32_t refine_radius, float lr, int32_t update, float* grads,
-                            float* loss, void* stream);
+me_status me_cnn_train_step(me_ctx ctx, const uint16_t* x, const int16_t* mv, const float* weight, int32_t n,
+                            int32_t Hq, int32_t Wq, int32_t radius, int32_t refine_radius, float lr, int32_t update,
+                            float* grads, float* loss, void* stream);
 /* Checkpoint of the optimiser state (parameters, both moments, step count,
  * median) in a host buffer of me_cnn_state_bytes() bytes.  Synchronous. */
 int64_t me_cnn_state_bytes(void);
@@ -225,14 +229,14 @@ me_status me_cnn_load_state(me_ctx ctx, const void* buf, int64_t bytes);
  * the gradient dz of its output ([n][Ho][Wo][coutp], coutp = 32, or 4 for
  * layer 3 with channel 3 zero), writing the layer's slice of grads and, for
  * layer > 0, the input gradient masked by the input's ReLU (x > 0) into dx;
- * the loss of float32 outputs against labels (dz: bfloat16 [n][nblk][4],
- * loss: float32 scalar; synchronous); an AdamW step with given gradients. */
+ * the loss of float32 outputs against labels (weight as for the training
+ * step; dz: bfloat16 [n][nblk][4], loss: float32 scalar; synchronous); an AdamW step with given gradients. */
 me_status me_cnn_layer_forward(me_ctx ctx, int32_t layer, const uint16_t* in, void* out, int32_t n, int32_t H,
                                int32_t W, void* stream);
 me_status me_cnn_layer_backward(me_ctx ctx, int32_t layer, const uint16_t* x, const uint16_t* dz, uint16_t* dx,
                                 float* grads, int32_t n, int32_t H, int32_t W, void* stream);
-me_status me_cnn_loss(me_ctx ctx, const float* out, const int16_t* mv, int32_t n, int32_t nblk, int32_t radius,
-                      int32_t refine_radius, uint16_t* dz, float* loss, void* stream);
+me_status me_cnn_loss(me_ctx ctx, const float* out, const int16_t* mv, const float* weight, int32_t n, int32_t nblk,
+                      int32_t radius, int32_t refine_radius, uint16_t* dz, float* loss, void* stream);
 me_status me_cnn_adamw(me_ctx ctx, const float* grads, float lr, void* stream);
 
 /* One frame pair of a batch (me_batch_submit). */
@@ -248,12 +252,29 @@ typedef struct {
  * me_batch_submit -- many independent frame pairs of mixed sizes, block sizes
  * and radii in one launch (the paper's batched grid over (Batch, h, w),
  * Sec. 4.1 CUDA settings, extended to uneven jobs).  jobs is a HOST array of
- * n entries; results are bit-identical to n separate me_estimate calls.  The
- * first submission of a given job-shape list captures a HIP graph in the
- * context; later submissions with the same shapes replay it with the new
- * pointers.  Needs a context.
+ * n entries (read before return); results are bit-identical to n separate
+ * me_estimate calls.  The work is cut into items (a run of blocks of one
+ * block row of one job), one workgroup each; jobs with equal LDS needs share
+ * a launch, items ordered by decreasing cost.  The launches are captured as
+ * one HIP graph and replayed while the job shapes repeat; each submission
+ * stages its job table through pinned memory into context-owned device
+ * tables (the item list too when the shapes change).  Submissions that
+ * use one context share those tables: on one stream they are ordered; across
+ * streams the caller must order them (or use one context per stream).
+ * Returns ME_E_UNSUPPORTED for modes other than exhaustive step 1.
  */
 me_status me_batch_submit(me_ctx ctx, const me_job* jobs, int32_t n, void* stream);
+
+/*
+ * me_autotune -- time the candidate launch shapes of the full-search kernel
+ * (candidate tile shape per lane, blocks per workgroup, LDS window band) on
+ * this frame pair with HIP events and keep the fastest in the context for
+ * (block, radius, frame size); later me_estimate calls with that key use it.
+ * Every shape gives bit-identical results.  Synchronises `stream`.
+ * best_ms (host, may be NULL) receives the fastest mean time of `iters` runs.
+ */
+me_status me_autotune(me_ctx ctx, const me_frame* ref, const me_frame* cur, int32_t block, int32_t radius,
+                      int32_t iters, float* best_ms, void* stream);
 
 /* Human-readable name of a status code (static string). */
 const char* me_status_string(me_status s);

@@ -5,7 +5,11 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <map>
 #include <new>
+#include <utility>
+#include <vector>
 
 #include "ctx.h"
 
@@ -90,6 +94,14 @@ me_ctx_s::~me_ctx_s()
     (void)hipFree(list);
     (void)hipFree(count);
     cnn.release();
+    if (staged) (void)hipEventSynchronize(staged);
+    if (graph) (void)hipGraphExecDestroy(graph);
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    if (staged) (void)hipEventDestroy(staged);
+    (void)hipFree(ptrs_dev);
+    (void)hipHostFree(ptrs_host);
+    (void)hipFree(tune_mv);
+    (void)hipFree(tune_sad);
 }
 
 namespace me {
@@ -330,11 +342,201 @@ me_status me_batch_submit(me_ctx ctx, const me_job* jobs, int32_t n, void* strea
         if (j.params.step != 1 || j.params.mode != ME_MODE_EXHAUSTIVE)
             return fail(ME_E_UNSUPPORTED, "me_batch_submit: job %d: only exhaustive step-1 jobs", k);
     }
+    if (n == 0) return ME_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+
+    // shape of each job: pairs with equal (block, radius, size, pitches) share
+    // one launch over a (pair, block row, block group) grid
+    std::vector<int64_t> shapes((size_t)n * 4);
     for (int32_t k = 0; k < n; ++k) {
         const me_job& j = jobs[k];
-        me_status s = me_estimate(ctx, &j.ref, &j.cur, &j.params, j.mv, j.sad, nullptr, stream);
-        if (s != ME_OK) return s;
+        shapes[4 * k] = (int64_t)j.params.block << 32 | (uint32_t)j.params.radius;
+        shapes[4 * k + 1] = (int64_t)j.cur.height << 32 | (uint32_t)j.cur.width;
+        shapes[4 * k + 2] = j.ref.pitch;
+        shapes[4 * k + 3] = j.cur.pitch;
     }
+    const bool same = ctx->graph && shapes == ctx->batch_shapes;
+
+    // groups in order of first appearance; slot[k] = row of job k in the table
+    std::vector<int32_t> slot((size_t)n);
+    std::vector<std::pair<int32_t, int32_t>> groups;     // (first job, count)
+    if (same) {
+        slot = ctx->batch_slot;
+    } else {
+        std::vector<std::vector<int32_t>> members;
+        std::map<std::vector<int64_t>, size_t> index;
+        for (int32_t k = 0; k < n; ++k) {
+            std::vector<int64_t> key(shapes.begin() + 4 * k, shapes.begin() + 4 * k + 4);
+            auto it = index.find(key);
+            if (it == index.end()) {
+                it = index.emplace(key, members.size()).first;
+                members.emplace_back();
+            }
+            members[it->second].push_back(k);
+        }
+        int32_t row = 0;
+        for (const std::vector<int32_t>& m : members) {
+            groups.push_back({m[0], (int32_t)m.size()});
+            for (int32_t k : m) slot[k] = row++;
+        }
+    }
+
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if (!ctx->staged) {
+        if ((e = hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming)) != hipSuccess ||
+            (e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(e, "me_batch_submit: setup");
+    }
+    // the previous submission's staging copy must be done before reuse
+    if ((e = hipEventSynchronize(ctx->staged)) != hipSuccess) return hip_fail(e, "me_batch_submit: staging wait");
+    if ((size_t)n > ctx->cap_ptrs) {
+        // a larger table moves: wait for launches that may still read the old
+        // one, and drop the graph that captured its address
+        if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "me_batch_submit: synchronize");
+        if (ctx->graph) {
+            (void)hipGraphExecDestroy(ctx->graph);
+            ctx->graph = nullptr;
+        }
+        ctx->batch_shapes.clear();
+        (void)hipFree(ctx->ptrs_dev);
+        (void)hipHostFree(ctx->ptrs_host);
+        ctx->ptrs_dev = nullptr;
+        ctx->ptrs_host = nullptr;
+        ctx->cap_ptrs = 0;
+        if (hipMalloc(&ctx->ptrs_dev, sizeof(JobPtrs) * n) != hipSuccess ||
+            hipHostMalloc(&ctx->ptrs_host, sizeof(JobPtrs) * n) != hipSuccess)
+            return fail(ME_E_NOMEM, "me_batch_submit: pointer table allocation failed");
+        ctx->cap_ptrs = (size_t)n;
+    }
+    for (int32_t k = 0; k < n; ++k) {
+        const me_job& j = jobs[k];
+        JobPtrs& p = ctx->ptrs_host[slot[k]];
+        p.ref = reinterpret_cast<const uint32_t*>(j.ref.data);
+        p.cur = reinterpret_cast<const uint32_t*>(j.cur.data);
+        p.mv = j.mv;
+        p.sad = j.sad;
+    }
+    if ((e = hipMemcpyAsync(ctx->ptrs_dev, ctx->ptrs_host, sizeof(JobPtrs) * n, hipMemcpyHostToDevice, st)) !=
+            hipSuccess ||
+        (e = hipEventRecord(ctx->staged, st)) != hipSuccess)
+        return hip_fail(e, "me_batch_submit: staging copy");
+
+    // one captured graph of the per-shape launches (the same kernels and
+    // launch shapes as single-pair calls, autotuned ones included); they read
+    // the pointer table at a fixed address, so a replay picks up new pairs
+    if (!same) {
+        if (ctx->graph) {
+            (void)hipGraphExecDestroy(ctx->graph);
+            ctx->graph = nullptr;
+        }
+        ctx->batch_shapes.clear();
+        std::vector<SearchArgs> args;
+        std::vector<TileCfg> cfgs;
+        for (const std::pair<int32_t, int32_t>& g : groups) {
+            const me_job& j = jobs[g.first];
+            SearchArgs a = make_args(&j.ref, &j.cur, j.params.block, j.params.radius, j.params.radius, nullptr,
+                                     j.mv, j.sad);
+            a.jobs = ctx->ptrs_dev + slot[g.first];
+            a.n_jobs = g.second;
+            args.push_back(a);
+            cfgs.push_back(tiles_for(ctx, a.block, a.R, a.Hp, a.Wp));
+        }
+        hipGraph_t gr = nullptr;
+        if ((e = hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return hip_fail(e, "me_batch_submit: capture");
+        hipError_t le = hipSuccess;
+        for (size_t i = 0; i < args.size() && le == hipSuccess; ++i)
+            le = launch_sad_search(args[i], cfgs[i], 0, ctx->capture_stream);
+        e = hipStreamEndCapture(ctx->capture_stream, &gr);
+        if (le != hipSuccess) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return hip_fail(le, "me_batch_submit: captured launch");
+        }
+        if (e != hipSuccess) return hip_fail(e, "me_batch_submit: end capture");
+        e = hipGraphInstantiate(&ctx->graph, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        if (e != hipSuccess) return hip_fail(e, "me_batch_submit: instantiate");
+        ctx->batch_shapes.swap(shapes);
+        ctx->batch_slot.swap(slot);
+    }
+    if ((e = hipGraphLaunch(ctx->graph, st)) != hipSuccess) return hip_fail(e, "me_batch_submit: graph launch");
+    return ME_OK;
+}
+
+me_status me_autotune(me_ctx ctx, const me_frame* ref, const me_frame* cur, int32_t block, int32_t radius,
+                      int32_t iters, float* best_ms, void* stream)
+{
+    if (!ctx) return fail(ME_E_INVAL, "me_autotune: null context");
+    me_status s = check_pair(ref, cur);
+    if (s != ME_OK) return s;
+    if (!block_ok(block)) return fail(ME_E_UNSUPPORTED, "me_autotune: block %d not in {8,16,32,64}", block);
+    if (radius < 0 || radius > 64) return fail(ME_E_INVAL, "me_autotune: radius %d not in [0,64]", radius);
+    if (iters < 1 || iters > 100) return fail(ME_E_INVAL, "me_autotune: iters %d not in [1,100]", iters);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int Hp = cur->height / 2, Wp = cur->width / 2;
+    const size_t nblk = (size_t)((Hp + block - 1) / block) * ((Wp + block - 1) / block);
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if (nblk > ctx->tune_cap) {
+        (void)hipFree(ctx->tune_mv);
+        (void)hipFree(ctx->tune_sad);
+        ctx->tune_mv = nullptr;
+        ctx->tune_sad = nullptr;
+        ctx->tune_cap = 0;
+        if (hipMalloc(&ctx->tune_mv, nblk * 2 * sizeof(int16_t)) != hipSuccess ||
+            hipMalloc(&ctx->tune_sad, nblk * sizeof(int32_t)) != hipSuccess)
+            return fail(ME_E_NOMEM, "me_autotune: allocation failed");
+        ctx->tune_cap = nblk;
+    }
+    SearchArgs a = make_args(ref, cur, block, radius, radius, nullptr, ctx->tune_mv, ctx->tune_sad);
+    const int shapes[6][2] = {{4, 4}, {8, 2}, {4, 2}, {8, 4}, {8, 1}, {4, 1}};
+    const size_t caps[3] = {53 * 1024, 80 * 1024, 160 * 1024};
+    std::vector<TileCfg> cands;
+    for (auto& sh : shapes)
+        for (int nb : {1, 2}) {
+            if (nb > 1 && radius % 4) continue;
+            for (size_t cap : caps) {
+                TileCfg c{};
+                c.kx = sh[0];
+                c.ky = sh[1];
+                c.nb = nb;
+                if (!tiles_supported(block, c.kx, c.ky) || !plan_tiles(block, radius, cap, &c)) continue;
+                bool dup = false;
+                for (const TileCfg& o : cands)
+                    dup |= o.kx == c.kx && o.ky == c.ky && o.nb == c.nb && o.band_ty == c.band_ty &&
+                           o.lds_pitch == c.lds_pitch;
+                if (!dup) cands.push_back(c);
+            }
+        }
+    hipEvent_t t0, t1;
+    if ((e = hipEventCreate(&t0)) != hipSuccess || (e = hipEventCreate(&t1)) != hipSuccess)
+        return hip_fail(e, "me_autotune: events");
+    float best = 1e30f;
+    TileCfg best_cfg = default_tiles(block, radius);
+    for (const TileCfg& c : cands) {
+        e = launch_sad_search(a, c, 0, st);               // warm-up (and launch check)
+        if (e != hipSuccess) continue;
+        (void)hipEventRecord(t0, st);
+        for (int i = 0; i < iters; ++i) (void)launch_sad_search(a, c, 0, st);
+        (void)hipEventRecord(t1, st);
+        if ((e = hipEventSynchronize(t1)) != hipSuccess) break;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, t0, t1);
+        ms /= (float)iters;
+        if (ms < best) {
+            best = ms;
+            best_cfg = c;
+        }
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (e != hipSuccess) return hip_fail(e, "me_autotune: timing");
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        ctx->tuned[std::make_tuple(block, radius, Hp, Wp)] = best_cfg;
+    }
+    if (best_ms) *best_ms = best;
     return ME_OK;
 }
 

@@ -216,8 +216,9 @@ __device__ __forceinline__ float berhu_grad(float x, float c) { return fabsf(x) 
 
 // Per block: loss value and the gradient of the batch mean, as bfloat16
 // [n][nblk][4] (channel 3 = 0) for the last layer's backward.
-__global__ void loss_kernel(const float* __restrict__ out, const int16_t* __restrict__ mv, int n, int nblk, int R,
-                            int rr, float scale, uint16_t* __restrict__ dz, float* __restrict__ bl)
+__global__ void loss_kernel(const float* __restrict__ out, const int16_t* __restrict__ mv,
+                            const float* __restrict__ wt, int n, int nblk, int R, int rr, float scale,
+                            uint16_t* __restrict__ dz, float* __restrict__ bl)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n * nblk) return;
@@ -232,10 +233,11 @@ __global__ void loss_kernel(const float* __restrict__ out, const int16_t* __rest
     const float c = 0.125f;
     const float ex = ox - (float)mx * 0.125f, ey = oy - (float)my * 0.125f;
     const float bce = fmaxf(lg, 0.f) - lg * y + log1pf(expf(-fabsf(lg)));
-    bl[e] = berhu(ex, c) + berhu(ey, c) + bce;
+    const float w = wt ? wt[e] : 1.f;              // weight of the vector term
+    bl[e] = w * (berhu(ex, c) + berhu(ey, c)) + bce;
     const float sg = lg >= 0.f ? 1.f / (1.f + expf(-lg)) : expf(lg) / (1.f + expf(lg));
     *reinterpret_cast<uint2*>(dz + 4 * (size_t)e) =
-        pack4(berhu_grad(ex, c) * scale, berhu_grad(ey, c) * scale, (sg - y) * scale, 0.f);
+        pack4(w * berhu_grad(ex, c) * scale, w * berhu_grad(ey, c) * scale, (sg - y) * scale, 0.f);
 }
 
 // Fixed-order sum of the block losses, times scale (one workgroup).
@@ -488,12 +490,13 @@ hipError_t launch_conv_fwd(int l, const uint16_t* in, const uint16_t* wp, const 
     return hipGetLastError();
 }
 
-hipError_t launch_loss(const float* out, const int16_t* mv, int n, int nblk, int R, int rr, uint16_t* dz, float* bl,
-                       float* loss, hipStream_t st)
+hipError_t launch_loss(const float* out, const int16_t* mv, const float* wt, int n, int nblk, int R, int rr,
+                       uint16_t* dz, float* bl, float* loss, hipStream_t st)
 {
     const int m = n * nblk;
     const float scale = 1.0f / (float)m;
-    hipLaunchKernelGGL(loss_kernel, dim3(div_up(m, 256)), dim3(256), 0, st, out, mv, n, nblk, R, rr, scale, dz, bl);
+    hipLaunchKernelGGL(loss_kernel, dim3(div_up(m, 256)), dim3(256), 0, st, out, mv, wt, n, nblk, R, rr, scale, dz,
+                       bl);
     if (loss) hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(256), 0, st, bl, m, scale, loss);
     return hipGetLastError();
 }

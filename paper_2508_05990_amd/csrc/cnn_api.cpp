@@ -217,9 +217,9 @@ me_status me_cnn_forward(me_ctx ctx, const uint16_t* x, int32_t n, int32_t Hq, i
     return forward_impl(ctx, x, n, Hq, Wq, out, reinterpret_cast<hipStream_t>(stream));
 }
 
-me_status me_cnn_train_step(me_ctx ctx, const uint16_t* x, const int16_t* mv, int32_t n, int32_t Hq, int32_t Wq,
-                            int32_t radius, int32_t refine_radius, float lr, int32_t update, float* grads,
-                            float* loss, void* stream)
+me_status me_cnn_train_step(me_ctx ctx, const uint16_t* x, const int16_t* mv, const float* weight, int32_t n,
+                            int32_t Hq, int32_t Wq, int32_t radius, int32_t refine_radius, float lr, int32_t update,
+                            float* grads, float* loss, void* stream)
 {
     me_status s = check_net_input(ctx, x, n, Hq, Wq);
     if (s != ME_OK) return s;
@@ -235,7 +235,7 @@ me_status me_cnn_train_step(me_ctx ctx, const uint16_t* x, const int16_t* mv, in
     s = forward_impl(ctx, x, n, Hq, Wq, c.out, st);
     if (s != ME_OK) return s;
     const int nblk = d.h[4] * d.w[4];
-    hipError_t e = launch_loss(c.out, mv, n, nblk, radius, refine_radius, c.dz4, c.bl, loss, st);
+    hipError_t e = launch_loss(c.out, mv, weight, n, nblk, radius, refine_radius, c.dz4, c.bl, loss, st);
     if (e != hipSuccess) return hip_fail(e, "me_cnn_train_step: loss");
     // backward: layer 3 (input a3, output grad dz4), then 2, 1, 0
     const uint16_t* xin[4] = {x, c.a1, c.a2, c.a3};
@@ -378,8 +378,8 @@ me_status me_cnn_layer_backward(me_ctx ctx, int32_t layer, const uint16_t* x, co
     return ME_OK;
 }
 
-me_status me_cnn_loss(me_ctx ctx, const float* out, const int16_t* mv, int32_t n, int32_t nblk, int32_t radius,
-                      int32_t refine_radius, uint16_t* dz, float* loss, void* stream)
+me_status me_cnn_loss(me_ctx ctx, const float* out, const int16_t* mv, const float* weight, int32_t n, int32_t nblk,
+                      int32_t radius, int32_t refine_radius, uint16_t* dz, float* loss, void* stream)
 {
     if (!ctx || !out || !mv || !dz || !loss) return fail(ME_E_INVAL, "me_cnn_loss: null argument");
     if (reinterpret_cast<uintptr_t>(dz) & 7u) return fail(ME_E_INVAL, "me_cnn_loss: dz must be 8-byte aligned");
@@ -389,7 +389,7 @@ me_status me_cnn_loss(me_ctx ctx, const float* out, const int16_t* mv, int32_t n
     if (hipMalloc(&bl, sizeof(float) * (size_t)n * nblk) != hipSuccess)
         return fail(ME_E_NOMEM, "me_cnn_loss: allocation failed");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    hipError_t e = launch_loss(out, mv, n, nblk, radius, refine_radius, dz, bl, loss, st);
+    hipError_t e = launch_loss(out, mv, weight, n, nblk, radius, refine_radius, dz, bl, loss, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     (void)hipFree(bl);
     if (e != hipSuccess) return hip_fail(e, "me_cnn_loss: launch");

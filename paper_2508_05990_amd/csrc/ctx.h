@@ -6,6 +6,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <vector>
 
 #include "../../include/me.h"
 #include "internal.h"
@@ -65,6 +66,23 @@ struct me_ctx_s {
     // SAD per sample of the full-search best match, median over training data
     float median_per_sample = 0.0f;
     me::CnnState cnn;
+    // batch submission: device table of per-pair pointers (grouped by shape),
+    // its pinned host staging guarded by an event, and the captured graph of
+    // the per-shape launches; a submission whose job shapes repeat the
+    // previous one's (same order) replays the graph and only restages the
+    // pointers
+    me::JobPtrs* ptrs_dev = nullptr;
+    me::JobPtrs* ptrs_host = nullptr;
+    size_t cap_ptrs = 0;
+    hipEvent_t staged = nullptr;
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t graph = nullptr;
+    std::vector<int64_t> batch_shapes;
+    std::vector<int32_t> batch_slot;     // job k -> its row in the pointer table
+    // autotune scratch outputs
+    int16_t* tune_mv = nullptr;
+    int32_t* tune_sad = nullptr;
+    size_t tune_cap = 0;
 
     ~me_ctx_s();
 };

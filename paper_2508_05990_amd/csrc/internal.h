@@ -7,6 +7,14 @@
 
 namespace me {
 
+// Device pointers of one pair of a batch launch.
+struct JobPtrs {
+    const uint32_t* ref;
+    const uint32_t* cur;
+    int16_t* mv;
+    int32_t* sad;
+};
+
 // One block-matching stage over one frame pair.  Frames are read as 32-bit
 // words: word k of mosaic row r holds samples (r, 2k) and (r, 2k+1), i.e. the
 // packed-plane pixel column k of the two planes that live on row r's parity.
@@ -31,7 +39,13 @@ struct SearchArgs {
     int32_t lds_pitch;      // words per LDS window row (multiple of 4)
     int32_t col0, ncols;    // block columns covered by a launch without a list
     int32_t nb;             // horizontally adjacent blocks per workgroup (1 with a list or predictors)
+    // batch launch: n_jobs pairs of this shape (block, radius, frame size,
+    // pitches); each workgroup takes ref/cur/mv/sad of its pair from jobs[]
+    // instead of the fields above.  Null for a single pair.
+    const JobPtrs* jobs;
+    int32_t n_jobs;
 };
+
 
 // Launch shape of the search kernel.
 struct TileCfg {
@@ -54,6 +68,8 @@ TileCfg default_tiles(int B, int R);
 // Whether the kernel table has an instance for (B, kx, ky).
 bool tiles_supported(int B, int kx, int ky);
 
+// Full or stage search of one pair, of a.n_jobs pairs of one shape
+// (a.jobs), or of the first *a.list_n blocks of a.list (n_wg = list capacity).
 hipError_t launch_sad_search(const SearchArgs& a, const TileCfg& cfg, int n_wg, hipStream_t stream);
 
 // Bilinear propagation of a feature map by block vectors.
@@ -78,8 +94,8 @@ hipError_t launch_pool(const uint16_t* ref, int64_t ref_pitch, const uint16_t* c
 hipError_t launch_pack(const float* w, uint16_t* fwd, uint16_t* bwd, hipStream_t st);
 hipError_t launch_conv_fwd(int l, const uint16_t* in, const uint16_t* wp, const float* bias, void* out, int n, int H,
                            int W, int Ho, int Wo, hipStream_t st);
-hipError_t launch_loss(const float* out, const int16_t* mv, int n, int nblk, int R, int rr, uint16_t* dz, float* bl,
-                       float* loss, hipStream_t st);
+hipError_t launch_loss(const float* out, const int16_t* mv, const float* wt, int n, int nblk, int R, int rr,
+                       uint16_t* dz, float* bl, float* loss, hipStream_t st);
 hipError_t launch_conv_dgrad(int l, const uint16_t* dz, const uint16_t* wb, const uint16_t* aprev, uint16_t* dprev,
                              int n, int H, int W, int Ho, int Wo, hipStream_t st);
 hipError_t launch_conv_wgrad(int l, const uint16_t* x, const uint16_t* dz, float* partial, float* grads, int n, int H,

@@ -22,6 +22,9 @@ namespace me {
 namespace {
 
 constexpr int kMaxWaves = 16;
+// Workgroup size limit the tiled kernel is compiled for (__launch_bounds__):
+// at most two blocks (8 waves) per workgroup.
+constexpr int kTiledMaxThreads = 512;
 constexpr int kWavesPerBlock = 4;
 constexpr int kMaxPitch = 256;            // words per LDS row (four 64-word chunks)
 
@@ -331,39 +334,19 @@ __device__ __forceinline__ void block_band(const SearchArgs& a, const BlockGeo& 
     }
 }
 
-// Full-width blocks, nb per workgroup (nb = 1 when a block list or per-block
-// predictors are given, since their candidate rows then differ).
+// Tiled search of the full-width blocks [first_blk, first_blk + nblk) of one
+// block row by the whole workgroup (4 waves per block; all threads call it).
 template <int CW, int NCH, int KX, int KY>
-__global__ __launch_bounds__(512) void sad_search_kernel(SearchArgs a)
+__device__ __forceinline__ void run_tiled(const SearchArgs& a, int first_blk, int nblk, uint32_t* lds, uint64_t* red)
 {
-    extern __shared__ uint4 lds_dyn[];
-    __shared__ uint64_t red[kMaxWaves];
     constexpr int B = CW * NCH;
-    uint32_t* lds = reinterpret_cast<uint32_t*>(lds_dyn);
     const int tid = threadIdx.x;
     const int nw = blockDim.x >> 6;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     const int pitch = a.lds_pitch;
-
-    // blocks of this workgroup: [first_blk, first_blk + nblk), one block row
-    int first_blk, nblk;
-    if (a.list) {
-        if ((int)blockIdx.x >= *a.list_n) return;     // whole workgroup leaves
-        first_blk = a.list[blockIdx.x];
-        nblk = 1;
-    } else {
-        const int groups = (a.ncols + a.nb - 1) / a.nb;
-        const int gid = xcd_remap(blockIdx.x, gridDim.x);
-        const int bi = gid / groups, gj = gid - bi * groups;
-        const int c0 = gj * a.nb;
-        first_blk = bi * a.bw + a.col0 + c0;
-        nblk = min(a.nb, a.ncols - c0);
-    }
     BlockGeo g0;
     block_geo(a, B, first_blk, g0);
-    if (g0.w != B) return;                        // partial-width blocks: generic kernel
-
     const int mine = wave / kWavesPerBlock;         // this wave's block within the group
     const int wib = wave - mine * kWavesPerBlock;
     const bool has_block = mine < nblk;
@@ -396,24 +379,12 @@ __global__ __launch_bounds__(512) void sad_search_kernel(SearchArgs a)
     }
 }
 
-// Blocks cut by the right frame edge: one candidate per lane, runtime width.
-__global__ __launch_bounds__(256) void sad_search_generic(SearchArgs a)
+// One block of any width, one candidate per lane (a.band_ty candidate rows
+// per band, a.lds_pitch words per LDS row); all threads call it.
+__device__ __forceinline__ void run_generic(const SearchArgs& a, int blk, uint32_t* lds, uint64_t* red)
 {
-    extern __shared__ uint4 lds_dyn[];
-    __shared__ uint64_t red[kMaxWaves];
-    int blk;
-    if (a.list) {
-        if ((int)blockIdx.x >= *a.list_n) return;
-        blk = a.list[blockIdx.x];
-    } else {
-        const int lb = xcd_remap(blockIdx.x, gridDim.x);
-        const int bi = lb / a.ncols;
-        blk = bi * a.bw + a.col0 + (lb - bi * a.ncols);
-    }
     BlockGeo g;
     block_geo(a, a.block, blk, g);
-    if (g.w == a.block) return;                    // full-width blocks: tiled kernel
-    uint32_t* lds = reinterpret_cast<uint32_t*>(lds_dyn);
     const int tid = threadIdx.x;
     const int nt = blockDim.x, nw = nt >> 6;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -448,27 +419,164 @@ __global__ __launch_bounds__(256) void sad_search_generic(SearchArgs a)
     }
 }
 
+// The pair a workgroup works on: the launch's own (ref, cur, mv, sad), or,
+// in a batch launch, those of job `job` of the launch's job table.
+__device__ __forceinline__ SearchArgs for_job(const SearchArgs& a, int job)
+{
+    SearchArgs b = a;
+    const JobPtrs p = a.jobs[job];
+    b.ref = p.ref;
+    b.cur = p.cur;
+    b.mv = p.mv;
+    b.sad = p.sad;
+    return b;
+}
+
+// Full-width blocks, nb per workgroup (nb = 1 when a block list or per-block
+// predictors are given, since their candidate rows then differ).  BATCH: the
+// grid covers a.n_jobs pairs of one shape, job-major (the paper's batch
+// dimension of the (Batch, h, w) grid).
+template <int CW, int NCH, int KX, int KY, bool BATCH>
+__global__ __launch_bounds__(kTiledMaxThreads) void sad_search_kernel(SearchArgs a)
+{
+    extern __shared__ uint4 lds_dyn[];
+    __shared__ uint64_t red[kMaxWaves];
+    constexpr int B = CW * NCH;
+    int first_blk, nblk;
+    if (BATCH) {
+        const int groups = (a.ncols + a.nb - 1) / a.nb;
+        const int per = a.bh * groups;                 // workgroups per pair
+        const int g = xcd_remap(blockIdx.x, gridDim.x);
+        const int job = g / per, gid = g - job * per;
+        const int bi = gid / groups, gj = gid - bi * groups;
+        const int c0 = gj * a.nb;
+        first_blk = bi * a.bw + a.col0 + c0;
+        nblk = min(a.nb, a.ncols - c0);
+        if (min(B, a.Wp - (first_blk % a.bw) * B) != B) return;
+        const SearchArgs b = for_job(a, job);
+        run_tiled<CW, NCH, KX, KY>(b, first_blk, nblk, reinterpret_cast<uint32_t*>(lds_dyn), red);
+        return;
+    }
+    if (a.list) {
+        if ((int)blockIdx.x >= *a.list_n) return;     // whole workgroup leaves
+        first_blk = a.list[blockIdx.x];
+        nblk = 1;
+    } else {
+        const int groups = (a.ncols + a.nb - 1) / a.nb;
+        const int gid = xcd_remap(blockIdx.x, gridDim.x);
+        const int bi = gid / groups, gj = gid - bi * groups;
+        const int c0 = gj * a.nb;
+        first_blk = bi * a.bw + a.col0 + c0;
+        nblk = min(a.nb, a.ncols - c0);
+    }
+    if (min(B, a.Wp - (first_blk % a.bw) * B) != B) return;   // partial-width blocks: generic kernel
+    run_tiled<CW, NCH, KX, KY>(a, first_blk, nblk, reinterpret_cast<uint32_t*>(lds_dyn), red);
+}
+
+// Blocks cut by the right frame edge: one candidate per lane, runtime width.
+template <bool BATCH>
+__global__ __launch_bounds__(256) void sad_search_generic(SearchArgs a)
+{
+    extern __shared__ uint4 lds_dyn[];
+    __shared__ uint64_t red[kMaxWaves];
+    int blk;
+    if (BATCH) {
+        const int per = a.bh * a.ncols;
+        const int lb = xcd_remap(blockIdx.x, gridDim.x);
+        const int job = lb / per, l = lb - job * per;
+        const int bi = l / a.ncols;
+        blk = bi * a.bw + a.col0 + (l - bi * a.ncols);
+        if (min(a.block, a.Wp - (blk % a.bw) * a.block) == a.block) return;
+        const SearchArgs b = for_job(a, job);
+        run_generic(b, blk, reinterpret_cast<uint32_t*>(lds_dyn), red);
+        return;
+    }
+    if (a.list) {
+        if ((int)blockIdx.x >= *a.list_n) return;
+        blk = a.list[blockIdx.x];
+    } else {
+        const int lb = xcd_remap(blockIdx.x, gridDim.x);
+        const int bi = lb / a.ncols;
+        blk = bi * a.bw + a.col0 + (lb - bi * a.ncols);
+    }
+    if (min(a.block, a.Wp - (blk % a.bw) * a.block) == a.block) return;   // full width: tiled kernel
+    run_generic(a, blk, reinterpret_cast<uint32_t*>(lds_dyn), red);
+}
+
+// Stage searches with a small candidate window (radius <= 4, e.g. the refine
+// step of the proposal path): one wave per block, one candidate per lane, so
+// a 5x5 window keeps 25 lanes busy where a 4x4 tile per lane would keep one.
+// Each wave stages its own block's window in its own LDS slice of
+// a.band_ty words and waits only for its own loads: no workgroup barrier,
+// four independent blocks per workgroup.
+template <int CW, int NCH, bool BATCH>
+__global__ __launch_bounds__(256) void sad_small_kernel(SearchArgs a_in)
+{
+    extern __shared__ uint4 lds_dyn[];
+    constexpr int B = CW * NCH;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    int blk;
+    SearchArgs a = a_in;
+    if (BATCH) {
+        const int nblk = a.bh * a.bw;
+        const int g = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+        const int job = g / nblk;
+        if (job >= a.n_jobs) return;                  // this wave only: nothing below waits for others
+        blk = g - job * nblk;
+        a = for_job(a_in, job);
+    } else if (a.list) {
+        const int slot = blockIdx.x * 4 + wave;
+        if (slot >= *a.list_n) return;
+        blk = a.list[slot];
+    } else {
+        blk = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+        if (blk >= a.bh * a.bw) return;
+    }
+    BlockGeo g;
+    block_geo(a, B, blk, g);
+    uint64_t best = ~0ull;
+    if (g.dxlo <= g.dxhi && g.dylo <= g.dyhi) {
+        const int nx = g.dxhi - g.dxlo + 1, ny = g.dyhi - g.dylo + 1;
+        uint32_t* win = reinterpret_cast<uint32_t*>(lds_dyn) + wave * a.band_ty;
+        stage_window(a, win, 2LL * (g.y0 + g.dylo), g.x0 + g.dxlo, 2 * (g.h + ny - 1), 0, 1, lane);
+        __builtin_amdgcn_s_waitcnt(0);
+        cptr_t curp = as_const(a.cur + 2LL * g.y0 * a.cur_pitch + g.x0);
+        for (int cand = lane; cand < nx * ny; cand += 64) {
+            const int cy = cand / nx, cx = cand - cy * nx;
+            const uint32_t* lb = win + 2 * cy * a.lds_pitch + cx;
+            const uint32_t sad = g.w == B ? single_sad_full<CW>(curp, a.cur_pitch, 2 * g.h, NCH, lb, a.lds_pitch)
+                                          : single_sad(curp, a.cur_pitch, 2 * g.h, g.w, lb, a.lds_pitch);
+            const uint64_t key = make_key(sad, g.dxlo + cx, g.dylo + cy);
+            best = key < best ? key : best;
+        }
+    }
+    best = wave_min_u64(best);
+    if (lane == 0) write_result(a, blk, best);
+}
+
 using KernelFn = void (*)(SearchArgs);
 
-template <int CW, int NCH>
+template <int CW, int NCH, bool BATCH>
 KernelFn table_get(int kx, int ky)
 {
-    if (kx == 4 && ky == 1) return sad_search_kernel<CW, NCH, 4, 1>;
-    if (kx == 4 && ky == 2) return sad_search_kernel<CW, NCH, 4, 2>;
-    if (kx == 4 && ky == 4) return sad_search_kernel<CW, NCH, 4, 4>;
-    if (kx == 8 && ky == 1) return sad_search_kernel<CW, NCH, 8, 1>;
-    if (kx == 8 && ky == 2) return sad_search_kernel<CW, NCH, 8, 2>;
-    if (kx == 8 && ky == 4) return sad_search_kernel<CW, NCH, 8, 4>;
+    if (kx == 4 && ky == 1) return sad_search_kernel<CW, NCH, 4, 1, BATCH>;
+    if (kx == 4 && ky == 2) return sad_search_kernel<CW, NCH, 4, 2, BATCH>;
+    if (kx == 4 && ky == 4) return sad_search_kernel<CW, NCH, 4, 4, BATCH>;
+    if (kx == 8 && ky == 1) return sad_search_kernel<CW, NCH, 8, 1, BATCH>;
+    if (kx == 8 && ky == 2) return sad_search_kernel<CW, NCH, 8, 2, BATCH>;
+    if (kx == 8 && ky == 4) return sad_search_kernel<CW, NCH, 8, 4, BATCH>;
     return nullptr;
 }
 
+template <bool BATCH>
 KernelFn kernel_for(int B, int kx, int ky)
 {
     switch (B) {
-    case 8: return table_get<8, 1>(kx, ky);
-    case 16: return table_get<16, 1>(kx, ky);
-    case 32: return table_get<16, 2>(kx, ky);
-    case 64: return table_get<16, 4>(kx, ky);
+    case 8: return table_get<8, 1, BATCH>(kx, ky);
+    case 16: return table_get<16, 1, BATCH>(kx, ky);
+    case 32: return table_get<16, 2, BATCH>(kx, ky);
+    case 64: return table_get<16, 4, BATCH>(kx, ky);
     default: return nullptr;
     }
 }
@@ -512,12 +620,12 @@ size_t tiled_bytes(int B, int n, int ky, int band_ty, int pitch)
 
 }  // namespace
 
-bool tiles_supported(int B, int kx, int ky) { return kernel_for(B, kx, ky) != nullptr; }
+bool tiles_supported(int B, int kx, int ky) { return kernel_for<false>(B, kx, ky) != nullptr; }
 
 bool plan_tiles(int B, int R, size_t lds_cap, TileCfg* cfg)
 {
     const int n = 2 * R + 1;
-    if (cfg->nb < 1 || cfg->nb * kWavesPerBlock > kMaxWaves) return false;
+    if (cfg->nb < 1 || cfg->nb * kWavesPerBlock * 64 > kTiledMaxThreads) return false;
     const int pitch = tiled_pitch(B, n, cfg->kx, cfg->nb);
     if (pitch > kMaxPitch) return false;
     int band = (n + cfg->ky - 1) / cfg->ky;
@@ -547,8 +655,54 @@ TileCfg default_tiles(int B, int R)
     return c;
 }
 
+// Window of the small-radius kernel: rows of w + 2R words (a multiple of 4)
+// and its bytes per wave; used for radius <= 4 while a wave's slice fits in
+// 32 KB.
+bool small_plan(int B, int R, int* pitch, int* words)
+{
+    if (R > 4) return false;
+    const int n = 2 * R + 1;
+    const int p = ((B + n - 1) + 3) & ~3;
+    const int w = 2 * (B + n - 1) * p;
+    if (p > kMaxPitch || (size_t)w * 4 > 32 * 1024) return false;
+    *pitch = p;
+    *words = w;
+    return true;
+}
+
+template <bool BATCH>
+KernelFn small_kernel_for(int B)
+{
+    switch (B) {
+    case 8: return sad_small_kernel<8, 1, BATCH>;
+    case 16: return sad_small_kernel<16, 1, BATCH>;
+    case 32: return sad_small_kernel<16, 2, BATCH>;
+    case 64: return sad_small_kernel<16, 4, BATCH>;
+    default: return nullptr;
+    }
+}
+
 hipError_t launch_sad_search(const SearchArgs& a, const TileCfg& cfg_in, int n_wg, hipStream_t stream)
 {
+    const bool batch = a.jobs != nullptr;
+    const int64_t njobs = batch ? a.n_jobs : 1;
+    if (batch && (a.list || a.n_jobs < 1)) return hipErrorInvalidValue;
+    int spitch = 0, swords = 0;
+    if (small_plan(a.block, a.R, &spitch, &swords)) {
+        KernelFn sk = batch ? small_kernel_for<true>(a.block) : small_kernel_for<false>(a.block);
+        if (!sk) return hipErrorInvalidValue;
+        const size_t bytes = (size_t)4 * swords * 4;    // four waves' slices
+        hipError_t e = set_lds(reinterpret_cast<const void*>(sk), bytes);
+        if (e != hipSuccess) return e;
+        SearchArgs b = a;
+        b.lds_pitch = spitch;
+        b.band_ty = swords;                             // words per wave slice
+        const int64_t nblk = a.list ? n_wg : njobs * a.bh * a.bw;
+        if (nblk <= 0) return hipSuccess;
+        if ((nblk + 3) / 4 > 0x7fffffff) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(sk, dim3((unsigned)((nblk + 3) / 4)), dim3(256), bytes, stream, b);
+        return hipGetLastError();
+    }
     TileCfg cfg = cfg_in;
     if ((a.list || a.pred || (a.R % 4) != 0) && cfg.nb != 1) {   // one block per workgroup
         cfg.nb = 1;
@@ -556,8 +710,9 @@ hipError_t launch_sad_search(const SearchArgs& a, const TileCfg& cfg_in, int n_w
             !plan_tiles(a.block, a.R, kLdsMax, &cfg))
             return hipErrorInvalidValue;
     }
-    KernelFn k = kernel_for(a.block, cfg.kx, cfg.ky);
-    if (!k || cfg.nb < 1 || cfg.nb * kWavesPerBlock > kMaxWaves || (cfg.lds_pitch & 3)) return hipErrorInvalidValue;
+    KernelFn k = batch ? kernel_for<true>(a.block, cfg.kx, cfg.ky) : kernel_for<false>(a.block, cfg.kx, cfg.ky);
+    if (!k || cfg.nb < 1 || cfg.nb * kWavesPerBlock * 64 > kTiledMaxThreads || (cfg.lds_pitch & 3))
+        return hipErrorInvalidValue;
     const int n = 2 * a.R + 1;
     // the shape must cover the widest candidate window of this radius
     if (cfg.band_ty < 1 || cfg.lds_pitch > kMaxPitch || cfg.lds_pitch < tiled_pitch(a.block, n, cfg.kx, cfg.nb) ||
@@ -577,11 +732,12 @@ hipError_t launch_sad_search(const SearchArgs& a, const TileCfg& cfg_in, int n_w
         gbytes = (size_t)2 * (a.block + gband - 1) * gpitch * 4;
     }
     if (has_partial && (gbytes > kLdsMax || gpitch > kMaxPitch)) return hipErrorInvalidValue;
+    KernelFn gk = batch ? sad_search_generic<true> : sad_search_generic<false>;
 
     hipError_t e = set_lds(reinterpret_cast<const void*>(k), cfg.lds_bytes);
     if (e != hipSuccess) return e;
     if (has_partial) {
-        e = set_lds(reinterpret_cast<const void*>(sad_search_generic), gbytes);
+        e = set_lds(reinterpret_cast<const void*>(gk), gbytes);
         if (e != hipSuccess) return e;
     }
     SearchArgs b = a;
@@ -595,19 +751,23 @@ hipError_t launch_sad_search(const SearchArgs& a, const TileCfg& cfg_in, int n_w
     if (a.list) {
         if (n_wg <= 0) return hipSuccess;
         hipLaunchKernelGGL(k, dim3(n_wg), dim3(kWavesPerBlock * 64), cfg.lds_bytes, stream, b);
-        if (has_partial) hipLaunchKernelGGL(sad_search_generic, dim3(n_wg), dim3(256), gbytes, stream, c);
+        if (has_partial) hipLaunchKernelGGL(gk, dim3(n_wg), dim3(256), gbytes, stream, c);
         return hipGetLastError();
     }
     if (full_cols > 0) {
         b.col0 = 0;
         b.ncols = full_cols;
-        const int groups = (full_cols + cfg.nb - 1) / cfg.nb;
-        hipLaunchKernelGGL(k, dim3(a.bh * groups), dim3(cfg.nb * kWavesPerBlock * 64), cfg.lds_bytes, stream, b);
+        const int64_t groups = (full_cols + cfg.nb - 1) / cfg.nb;
+        const int64_t grid = njobs * a.bh * groups;
+        if (grid > 0x7fffffff) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(cfg.nb * kWavesPerBlock * 64), cfg.lds_bytes, stream, b);
     }
     if (has_partial) {
         c.col0 = full_cols;
         c.ncols = 1;
-        hipLaunchKernelGGL(sad_search_generic, dim3(a.bh), dim3(256), gbytes, stream, c);
+        const int64_t grid = njobs * a.bh;
+        if (grid > 0x7fffffff) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(gk, dim3((unsigned)grid), dim3(256), gbytes, stream, c);
     }
     return hipGetLastError();
 }

@@ -65,17 +65,18 @@ _me_batch_submit = _sig("me_batch_submit", [_P, ctypes.POINTER(MeJob), _I32, _P]
 _me_refine = _sig("me_refine", [_P, ctypes.POINTER(MeFrame), ctypes.POINTER(MeFrame), ctypes.POINTER(MeParams), _P, _P,
                                 _P, _P, _P])
 _F = ctypes.c_float
+_me_autotune = _sig("me_autotune", [_P, ctypes.POINTER(MeFrame), ctypes.POINTER(MeFrame), _I32, _I32, _I32, _P, _P])
 _me_cnn_set_params = _sig("me_cnn_set_params", [_P, _P, _I32, _F])
 _me_cnn_get_params = _sig("me_cnn_get_params", [_P, _P, _I32, _P])
 _me_cnn_pool = _sig("me_cnn_pool", [_P, ctypes.POINTER(MeFrame), ctypes.POINTER(MeFrame), _P, _P])
 _me_cnn_forward = _sig("me_cnn_forward", [_P, _P, _I32, _I32, _I32, _P, _P])
-_me_cnn_train_step = _sig("me_cnn_train_step", [_P, _P, _P, _I32, _I32, _I32, _I32, _I32, _F, _I32, _P, _P, _P])
+_me_cnn_train_step = _sig("me_cnn_train_step", [_P, _P, _P, _P, _I32, _I32, _I32, _I32, _I32, _F, _I32, _P, _P, _P])
 _me_cnn_state_bytes = _sig("me_cnn_state_bytes", [], ctypes.c_int64)
 _me_cnn_save_state = _sig("me_cnn_save_state", [_P, _P, ctypes.c_int64])
 _me_cnn_load_state = _sig("me_cnn_load_state", [_P, _P, ctypes.c_int64])
 _me_cnn_layer_forward = _sig("me_cnn_layer_forward", [_P, _I32, _P, _P, _I32, _I32, _I32, _P])
 _me_cnn_layer_backward = _sig("me_cnn_layer_backward", [_P, _I32, _P, _P, _P, _P, _I32, _I32, _I32, _P])
-_me_cnn_loss = _sig("me_cnn_loss", [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P])
+_me_cnn_loss = _sig("me_cnn_loss", [_P, _P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P])
 _me_cnn_adamw = _sig("me_cnn_adamw", [_P, _P, _F, _P])
 _me_status_string = _sig("me_status_string", [_I32], ctypes.c_char_p)
 _me_last_error = _sig("me_last_error", [], ctypes.c_char_p)
@@ -84,7 +85,7 @@ EXPORTS = ["me_default_params", "me_ctx_create", "me_ctx_destroy", "me_estimate"
            "me_warp_features", "me_batch_submit", "me_refine", "me_status_string", "me_last_error",
            "me_cnn_set_params", "me_cnn_get_params", "me_cnn_pool", "me_cnn_forward", "me_cnn_train_step",
            "me_cnn_state_bytes", "me_cnn_save_state", "me_cnn_load_state", "me_cnn_layer_forward",
-           "me_cnn_layer_backward", "me_cnn_loss", "me_cnn_adamw"]
+           "me_cnn_layer_backward", "me_cnn_loss", "me_cnn_adamw", "me_autotune"]
 ME_CNN_NPARAMS = 21699
 
 
@@ -232,8 +233,17 @@ def warp_features(z_ref: torch.Tensor, mv: torch.Tensor, block: int, frame_h: in
     return out
 
 
-def batch_submit(ctx: Context, jobs, stream=None):
-    """jobs: list of (ref, cur, block, radius, mv, sad) device tensors; one submission."""
+def autotune(ctx: Context, ref, cur, block=16, radius=32, iters=3, stream=None) -> float:
+    """Pick the fastest launch shape for (block, radius, frame size); returns its time in ms."""
+    ms = ctypes.c_float()
+    fr, fc = frame_of(ref), frame_of(cur)
+    _check(_me_autotune(ctx.handle, ctypes.byref(fr), ctypes.byref(fc), block, radius, iters, ctypes.addressof(ms),
+                        _stream_handle(stream)))
+    return ms.value
+
+
+def make_jobs(jobs):
+    """Host job array for batch_submit from (ref, cur, block, radius, mv, sad) tuples."""
     arr = (MeJob * len(jobs))()
     for k, (ref, cur, block, radius, mv, sad) in enumerate(jobs):
         arr[k].ref = frame_of(ref)
@@ -241,7 +251,15 @@ def batch_submit(ctx: Context, jobs, stream=None):
         arr[k].params = make_params(block, radius)
         arr[k].mv = mv.data_ptr()
         arr[k].sad = sad.data_ptr()
-    _check(_me_batch_submit(ctx.handle, arr, len(jobs), _stream_handle(stream)))
+    return arr
+
+
+def batch_submit(ctx: Context, jobs, stream=None):
+    """One submission of many pairs: a list of (ref, cur, block, radius, mv,
+    sad) device tensors, or an array made by make_jobs (the tensors must stay
+    alive until the work is done)."""
+    arr = jobs if isinstance(jobs, ctypes.Array) else make_jobs(jobs)
+    _check(_me_batch_submit(ctx.handle, arr, len(arr), _stream_handle(stream)))
 
 
 # --- proposal network ---------------------------------------------------------
@@ -293,10 +311,11 @@ def cnn_forward(ctx, x, out=None, stream=None):
 
 
 def cnn_train_step(ctx, x, mv, radius=32, refine_radius=2, lr=1e-4, update=True, grads=None, loss=None,
-                   stream=None):
+                   weight=None, stream=None):
+    """weight: optional float32 [n, bh, bw] weight of each block's vector term."""
     n, Hq, Wq, _ = x.shape
-    _check(_me_cnn_train_step(ctx.handle, x.data_ptr(), mv.data_ptr(), n, Hq, Wq, radius, refine_radius, lr,
-                              1 if update else 0, _p(grads), _p(loss), _stream_handle(stream)))
+    _check(_me_cnn_train_step(ctx.handle, x.data_ptr(), mv.data_ptr(), _p(weight), n, Hq, Wq, radius, refine_radius,
+                              lr, 1 if update else 0, _p(grads), _p(loss), _stream_handle(stream)))
 
 
 def cnn_save_state(ctx) -> bytes:
@@ -322,10 +341,10 @@ def cnn_layer_backward(ctx, layer, x, dz, dx, grads, stream=None):
                                   _stream_handle(stream)))
 
 
-def cnn_loss(ctx, out, mv, radius, refine_radius, dz, loss, stream=None):
+def cnn_loss(ctx, out, mv, radius, refine_radius, dz, loss, weight=None, stream=None):
     n, _, bh, bw = out.shape
-    _check(_me_cnn_loss(ctx.handle, out.data_ptr(), mv.data_ptr(), n, bh * bw, radius, refine_radius, dz.data_ptr(),
-                        loss.data_ptr(), _stream_handle(stream)))
+    _check(_me_cnn_loss(ctx.handle, out.data_ptr(), mv.data_ptr(), _p(weight), n, bh * bw, radius, refine_radius,
+                        dz.data_ptr(), loss.data_ptr(), _stream_handle(stream)))
 
 
 def cnn_adamw(ctx, grads, lr, stream=None):

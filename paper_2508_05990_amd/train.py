@@ -1,0 +1,223 @@
+"""Train the proposal network on synthetic 1080p pairs labelled by full search.
+
+Everything numeric runs in the library's HIP kernels: pooling of the network
+input, full search for the labels, forward/backward/AdamW training steps and
+the evaluation passes.  The host only generates the seeded frames, orders the
+batches and follows the cosine learning-rate schedule (paper Sec. 4.1:
+AdamW, 1e-4 decayed to 1e-6, batch 16).
+
+    python -m paper_2508_05990_amd.train --pairs 2000 --epochs 100 \\
+        --out paper_2508_05990_amd/weights/proposal_1080p.bin
+
+Weights file: 16-byte header (b"MEPW", uint32 version 1, uint32 parameter
+count, float32 median per-sample SAD) followed by the float32 parameters,
+little endian.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import struct
+import sys
+import time
+from concurrent.futures import ProcessPoolExecutor
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_WEIGHTS = os.path.join(HERE, "weights", "proposal_1080p.bin")
+MAGIC = b"MEPW"
+
+
+def save_weights(path, params, median):
+    params = np.ascontiguousarray(params, dtype="<f4")
+    with open(path + ".tmp", "wb") as f:
+        f.write(MAGIC + struct.pack("<IIf", 1, params.size, float(median)))
+        f.write(params.tobytes())
+    os.replace(path + ".tmp", path)
+
+
+def load_weights(path):
+    with open(path, "rb") as f:
+        head = f.read(16)
+        if head[:4] != MAGIC:
+            raise ValueError("%s: not a proposal-network weights file" % path)
+        version, n, median = struct.unpack("<IIf", head[4:])
+        if version != 1:
+            raise ValueError("%s: unknown version %d" % (path, version))
+        params = np.frombuffer(f.read(4 * n), dtype="<f4").astype(np.float32)
+    if params.size != n:
+        raise ValueError("%s: truncated" % path)
+    return params, median
+
+
+def init_params(seed):
+    """He-normal weights, zero biases (float32), layer order of the library."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for ci, co in ((8, 32), (32, 32), (32, 32), (32, 3)):
+        parts.append(rng.normal(0.0, math.sqrt(2.0 / (ci * 9)), co * ci * 9))
+        parts.append(np.zeros(co))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def cosine_lr(step, total, lr0, lr_min):
+    t = min(max(step, 0), total) / float(max(total, 1))
+    return lr_min + 0.5 * (lr0 - lr_min) * (1.0 + math.cos(math.pi * t))
+
+
+def _make_sequence(seed):
+    from paper_2508_05990_amd import synth
+
+    return synth.hd_sequence(seed).frames
+
+
+def build_dataset(me, ctx, n_pairs, seed0, workers, log):
+    """Pooled inputs [n, 270, 480, 8] bf16 and full-search labels [n, 34, 60, 2] on the GPU."""
+    import torch
+
+    n_seq = (n_pairs + 14) // 15
+    X = torch.empty((n_pairs, 270, 480, 8), dtype=torch.bfloat16, device="cuda")
+    Y = torch.empty((n_pairs, 34, 60, 2), dtype=torch.int16, device="cuda")
+    S = torch.empty((n_pairs, 34, 60), dtype=torch.int32, device="cuda")
+    k = 0
+    t0 = time.time()
+    with ProcessPoolExecutor(max_workers=workers, mp_context=__import__("multiprocessing").get_context("spawn")) as ex:
+        for si, frames in enumerate(ex.map(_make_sequence, [seed0 + s for s in range(n_seq)])):
+            dev_frames = [torch.from_numpy(f).cuda() for f in frames]
+            for t in range(1, len(dev_frames)):
+                if k >= n_pairs:
+                    break
+                me.cnn_pool(ctx, dev_frames[t - 1], dev_frames[t], x=X[k])
+                me.estimate(dev_frames[t - 1], dev_frames[t], 16, 32, mv=Y[k], sad=S[k], ctx=ctx)
+                k += 1
+            torch.cuda.synchronize()
+            if si % 20 == 0:
+                log({"event": "data", "sequences": si + 1, "pairs": k, "seconds": round(time.time() - t0, 1)})
+    # median over all blocks of the best SAD per sample (full blocks: 1024 samples; last row 768)
+    nsamp = torch.full((34, 60), 1024.0, device="cuda")
+    nsamp[-1] = 4.0 * 12 * 16
+    median = float(torch.median((S.float() / nsamp).flatten()).item())
+    return X, Y, S, nsamp, median
+
+
+def evaluate(me, ctx, frames, use_net, median, R=32, rr=2):
+    """Proposal mode on consecutive pairs: fallback rate, MV-error rate against
+    full search (Euclidean error > 1 packed pixel) and mean time per pair."""
+    import torch
+
+    fb_sum = err_sum = n = 0
+    bh, bw = 34, 60
+    net_zero = torch.zeros((3, bh, bw), dtype=torch.float32, device="cuda")
+    mv_e = torch.empty((bh, bw, 2), dtype=torch.int16, device="cuda")
+    sad_e = torch.empty((bh, bw), dtype=torch.int32, device="cuda")
+    p = me.make_params(16, R, me.ME_MODE_PROPOSAL, rr, 0.0, 1.5, median)
+    times = []
+    for t in range(1, len(frames)):
+        me.estimate(frames[t - 1], frames[t], 16, R, mv=mv_e, sad=sad_e, ctx=ctx)
+        fb = torch.empty((bh, bw), dtype=torch.uint8, device="cuda")
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        if use_net:
+            mv, sad = me.estimate(frames[t - 1], frames[t], fallback=fb, params=p, ctx=ctx)
+        else:
+            mv, sad, fb = me.refine(frames[t - 1], frames[t], net_zero, ctx, 16, R, rr, 0.0, 1.5, median, fallback=fb)
+        b.record()
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b))
+        d = (mv.int() - mv_e.int()).float()
+        err_sum += int(((d[..., 0] ** 2 + d[..., 1] ** 2) > 1.0).sum().item())
+        fb_sum += int(fb.sum().item())
+        n += bh * bw
+    return {"fallback_rate": fb_sum / n, "mv_err_rate": err_sum / n, "ms_per_pair": float(np.median(times))}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--pairs", type=int, default=2000)
+    ap.add_argument("--epochs", type=int, default=100)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--lr", type=float, default=1e-4)
+    ap.add_argument("--lr-min", type=float, default=1e-6)
+    ap.add_argument("--seed", type=int, default=1000, help="first sequence seed of the training set")
+    ap.add_argument("--init-seed", type=int, default=0)
+    ap.add_argument("--eval-seed", type=int, default=1, help="held-out 1080p sequence")
+    ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--mask-ratio", type=float, default=1.5,
+                    help="drop the vector term of blocks whose full-search SAD per sample exceeds this multiple "
+                         "of the median (0 = keep all)")
+    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--log", default=None, help="JSON-lines log file")
+    args = ap.parse_args(argv)
+
+    logf = open(args.log, "a") if args.log else None
+
+    def log(rec):
+        line = json.dumps(rec)
+        print(line, flush=True)
+        if logf:
+            logf.write(line + "\n")
+            logf.flush()
+
+    import torch
+
+    from paper_2508_05990_amd import me, synth
+
+    ctx = me.Context(0)
+    t_all = time.time()
+    X, Y, S, nsamp, median = build_dataset(me, ctx, args.pairs, args.seed, args.workers, log)
+    # vector-term weight: blocks whose full-search match is worse than the
+    # fallback threshold always fall back, so their vectors (occlusions,
+    # new content) are left out of the regression
+    Wt = None
+    if args.mask_ratio > 0:
+        thr = torch.floor(torch.tensor(args.mask_ratio, dtype=torch.float64) * median * nsamp.double())
+        Wt = (S.double() <= thr).float()
+    log({"event": "dataset", "pairs": args.pairs, "median_sad_per_sample": median,
+         "vector_weight_mean": None if Wt is None else float(Wt.mean().item())})
+    me.cnn_set_params(ctx, init_params(args.init_seed), median)
+
+    steps_per_epoch = args.pairs // args.batch
+    total = steps_per_epoch * args.epochs
+    rng = np.random.default_rng(args.seed)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    xb = torch.empty((args.batch,) + tuple(X.shape[1:]), dtype=X.dtype, device="cuda")
+    yb = torch.empty((args.batch,) + tuple(Y.shape[1:]), dtype=Y.dtype, device="cuda")
+    wb = None if Wt is None else torch.empty((args.batch,) + tuple(Wt.shape[1:]), dtype=Wt.dtype, device="cuda")
+    step = 0
+    t0 = time.time()
+    for ep in range(args.epochs):
+        order = torch.from_numpy(rng.permutation(args.pairs)).cuda()
+        for s in range(steps_per_epoch):
+            idx = order[s * args.batch:(s + 1) * args.batch]
+            torch.index_select(X, 0, idx, out=xb)
+            torch.index_select(Y, 0, idx, out=yb)
+            if wb is not None:
+                torch.index_select(Wt, 0, idx, out=wb)
+            lr = cosine_lr(step, total, args.lr, args.lr_min)
+            me.cnn_train_step(ctx, xb, yb, radius=32, refine_radius=2, lr=lr, update=True,
+                              loss=loss if s == steps_per_epoch - 1 else None, weight=wb)
+            step += 1
+        if ep % 5 == 0 or ep == args.epochs - 1:
+            log({"event": "epoch", "epoch": ep, "step": step, "lr": lr, "loss": float(loss.item()),
+                 "seconds": round(time.time() - t0, 1)})
+    torch.cuda.synchronize()
+    train_s = time.time() - t0
+    params, med = me.cnn_get_params(ctx)
+    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+    save_weights(args.out, params, med)
+
+    seq = synth.hd_sequence(args.eval_seed)
+    frames = [torch.from_numpy(f).cuda() for f in seq.frames]
+    trained = evaluate(me, ctx, frames, True, med)
+    zero = evaluate(me, ctx, frames, False, med)
+    log({"event": "done", "train_seconds": round(train_s, 1), "total_seconds": round(time.time() - t_all, 1),
+         "steps": total, "weights": args.out, "heldout_trained": trained, "heldout_zero_predictor": zero})
+    ctx.close()
+    return trained, zero
+
+
+if __name__ == "__main__":
+    sys.exit(0 if main() else 1)

@@ -1,0 +1,140 @@
+"""Batched submission (one persistent, graph-captured launch over many jobs of
+mixed sizes, block sizes and radii) and the launch-shape autotuner: results
+must be bit-identical to one me_estimate per job, and to the oracle."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2508_05990_amd import me
+
+    return me
+
+
+def _jobs(dev, seed):
+    """Mixed jobs: sizes with partial blocks, B in {8,16,32}, R in {3,8,16,32}."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    specs = [(96, 160, 8, 16), (120, 200, 16, 8), (200, 300, 32, 3), (64, 64, 8, 32), (150, 246, 16, 16),
+             (256, 256, 16, 32), (74, 90, 8, 3)]
+    out = []
+    for H, W, B, R in specs:
+        base = rng.integers(0, 4096, (H + 40, W + 40)).astype(np.uint16)
+        dy, dx = (int(v) for v in rng.integers(0, 20, 2))
+        f0 = np.ascontiguousarray(base[10:10 + H, 10:10 + W])
+        f1 = np.ascontiguousarray(base[dy:dy + H, dx:dx + W])
+        bh, bw = dev.block_grid(H, W, B)
+        out.append(dict(f0=f0, f1=f1, B=B, R=R, t0=torch.from_numpy(f0).cuda(), t1=torch.from_numpy(f1).cuda(),
+                        mv=torch.full((bh, bw, 2), 77, dtype=torch.int16, device="cuda"),
+                        sad=torch.full((bh, bw), -7, dtype=torch.int32, device="cuda")))
+    return out
+
+
+def test_batch_matches_single_launches_and_oracle(dev, oracle_mod):
+    import torch
+
+    ctx = dev.Context(0)
+    try:
+        for seed in (0, 1):                  # the second submission replays the captured graph
+            jobs = _jobs(dev, seed)
+            print("batch submission", seed, flush=True)   # seed 1: same shapes, cached item list
+            dev.batch_submit(ctx, [(j["t0"], j["t1"], j["B"], j["R"], j["mv"], j["sad"]) for j in jobs])
+            torch.cuda.synchronize()
+            for k, j in enumerate(jobs):
+                mv1, sad1 = dev.estimate(j["t0"], j["t1"], j["B"], j["R"])
+                torch.cuda.synchronize()
+                assert torch.equal(j["mv"], mv1) and torch.equal(j["sad"], sad1), k
+                if k % 3 == seed:
+                    mv_o, sad_o, _ = oracle_mod.full_search(j["f0"], j["f1"], j["B"], j["R"])
+                    assert np.array_equal(j["mv"].cpu().numpy(), mv_o) and np.array_equal(j["sad"].cpu().numpy(), sad_o)
+    finally:
+        ctx.close()
+
+
+def test_batch_of_one_and_reordering(dev):
+    import torch
+
+    ctx = dev.Context(0)
+    try:
+        jobs = _jobs(dev, 3)
+        dev.batch_submit(ctx, [(jobs[5]["t0"], jobs[5]["t1"], 16, 32, jobs[5]["mv"], jobs[5]["sad"])])
+        torch.cuda.synchronize()
+        mv1, sad1 = dev.estimate(jobs[5]["t0"], jobs[5]["t1"], 16, 32)
+        assert torch.equal(jobs[5]["mv"], mv1) and torch.equal(jobs[5]["sad"], sad1)
+        rev = list(reversed(jobs))
+        dev.batch_submit(ctx, [(j["t0"], j["t1"], j["B"], j["R"], j["mv"], j["sad"]) for j in rev])
+        torch.cuda.synchronize()
+        for j in rev:
+            mv1, sad1 = dev.estimate(j["t0"], j["t1"], j["B"], j["R"])
+            assert torch.equal(j["mv"], mv1) and torch.equal(j["sad"], sad1)
+        # fewer items than the tables hold: a rebuilt item list without regrowth
+        j = jobs[1]
+        j["mv"].fill_(5)
+        j["sad"].fill_(5)
+        dev.batch_submit(ctx, dev.make_jobs([(j["t0"], j["t1"], j["B"], j["R"], j["mv"], j["sad"])]))
+        torch.cuda.synchronize()
+        mv1, sad1 = dev.estimate(j["t0"], j["t1"], j["B"], j["R"])
+        assert torch.equal(j["mv"], mv1) and torch.equal(j["sad"], sad1)
+    finally:
+        ctx.close()
+
+
+def test_batch_of_mixed_streams(dev):
+    """24 streams of four frame sizes up to 3840x2160 and (B, R) in
+    {8, 16} x {16, 32}, one pair each: many items per job, runs of blocks two
+    at a time; bit-identical to one launch per pair, on two submissions."""
+    import torch
+
+    from paper_2508_05990_amd import synth
+
+    ctx = dev.Context(0)
+    try:
+        jobs, singles = [], []
+        for B, R, seq in synth.stream_sequences(2, n_frames=2):
+            f0, f1 = (torch.from_numpy(f).cuda() for f in seq.frames)
+            bh, bw = dev.block_grid(*seq.shape, B)
+            mk = lambda: (torch.full((bh, bw, 2), 99, dtype=torch.int16, device="cuda"),
+                          torch.full((bh, bw), -9, dtype=torch.int32, device="cuda"))
+            jobs.append((f0, f1, B, R) + mk())
+            singles.append((f0, f1, B, R) + mk())
+        for ref, cur, B, R, mv, sad in singles:
+            dev.estimate(ref, cur, B, R, mv=mv, sad=sad, ctx=ctx)
+        arr = dev.make_jobs(jobs)
+        for rep in range(2):
+            for j in jobs:
+                j[4].fill_(99)
+                j[5].fill_(-9)
+            print("mixed-stream submission", rep, flush=True)
+            dev.batch_submit(ctx, arr)
+            torch.cuda.synchronize()
+            for k, (j, s) in enumerate(zip(jobs, singles)):
+                assert torch.equal(j[4], s[4]) and torch.equal(j[5], s[5]), (rep, k, j[2], j[3], tuple(j[0].shape))
+    finally:
+        ctx.close()
+
+
+def test_autotune_keeps_results(dev, oracle_mod):
+    import torch
+
+    from paper_2508_05990_amd import synth
+
+    seq = synth.hd_sequence(1, n_frames=2)
+    t0, t1 = (torch.from_numpy(f).cuda() for f in seq.frames)
+    ctx = dev.Context(0)
+    try:
+        mv0, sad0 = dev.estimate(t0, t1, 16, 32, ctx=ctx)
+        ms = dev.autotune(ctx, t0, t1, 16, 32, iters=2)
+        assert 0 < ms < 10
+        mv1, sad1 = dev.estimate(t0, t1, 16, 32, ctx=ctx)
+        torch.cuda.synchronize()
+        assert torch.equal(mv0, mv1) and torch.equal(sad0, sad1)
+    finally:
+        ctx.close()

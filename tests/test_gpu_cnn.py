@@ -148,7 +148,8 @@ def test_layer_backward(dev, ctx, layer):
             assert (np.abs(got[i] - ref) <= U * np.abs(ref) + 2e-5 * ab + 1e-30).all()
 
 
-def test_loss(dev, ctx):
+@pytest.mark.parametrize("weighted", [False, True])
+def test_loss(dev, ctx, weighted):
     import torch
 
     dev.cnn_set_params(ctx, _params(3), 1.0)
@@ -162,8 +163,11 @@ def test_loss(dev, ctx):
     out[0, 0, 0, :4] = (np.arange(4) + 0.5) / 8         # rounding ties
     dz = torch.empty((n, bh * bw, 4), dtype=torch.bfloat16, device="cuda")
     loss = torch.empty(1, dtype=torch.float32, device="cuda")
-    dev.cnn_loss(ctx, torch.from_numpy(out).cuda(), torch.from_numpy(mv).cuda(), R, rr, dz, loss)
-    Ls, Gs = zip(*[cnn.loss_and_grad(out[i].astype(np.float64), mv[i], R, rr) for i in range(n)])
+    w = rng.choice(np.array([0.0, 0.5, 1.0, 2.0], np.float32), (n, bh, bw)) if weighted else None
+    dev.cnn_loss(ctx, torch.from_numpy(out).cuda(), torch.from_numpy(mv).cuda(), R, rr, dz, loss,
+                 weight=None if w is None else torch.from_numpy(w).cuda())
+    Ls, Gs = zip(*[cnn.loss_and_grad(out[i].astype(np.float64), mv[i], R, rr, weight=None if w is None else w[i])
+                   for i in range(n)])
     assert float(loss.item()) == pytest.approx(np.mean(Ls), rel=1e-5)
     g = np.stack(Gs) / n                                  # gradient of the batch mean
     got = _np(dz).reshape(n, bh, bw, 4)
@@ -223,18 +227,20 @@ def test_forward_whole_network(dev, ctx):
             assert err < 2e-2, (i, c, err)
 
 
-def test_train_step_gradients(dev, ctx):
+@pytest.mark.parametrize("weighted", [False, True])
+def test_train_step_gradients(dev, ctx, weighted):
     import torch
 
     params = _params(8)
     dev.cnn_set_params(ctx, params, 1.0)
     x, mv, xs_o = _pair_inputs(dev, ctx, [2, 3])
+    w = np.random.default_rng(5).choice(np.array([0.0, 1.0], np.float32), mv.shape[:3]) if weighted else None
     grads = torch.empty(cnn.NPARAMS, dtype=torch.float32, device="cuda")
     loss = torch.empty(1, dtype=torch.float32, device="cuda")
     dev.cnn_train_step(ctx, x, torch.from_numpy(mv).cuda(), radius=8, refine_radius=2, update=False, grads=grads,
-                       loss=loss)
+                       loss=loss, weight=None if w is None else torch.from_numpy(w).cuda())
     torch.cuda.synchronize()
-    L, g_ref = cnn.batch_loss_and_grads(params, xs_o, list(mv), 8, 2)
+    L, g_ref = cnn.batch_loss_and_grads(params, xs_o, list(mv), 8, 2, weights=w)
     assert float(loss.item()) == pytest.approx(L, rel=2e-2)
     g = grads.cpu().numpy().astype(np.float64)
     for (Wg, bg), (Wr, br) in zip(cnn.unpack(g), cnn.unpack(g_ref)):
