@@ -28,7 +28,7 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the search kernel from rocprofv3 FETCH_SIZE/WRITE_SIZE
 # (scaled by a plain-copy calibration: FETCH x2, WRITE x1), valid for the
 # kernel source with this SHA-256 prefix only; reported as null otherwise.
-SAD_TRAFFIC = {"source_sha256_16": "a13e0bc5dbc1bcf8", "bytes": 7929.1 * 1024 * 2 + 16.1 * 1024}
+SAD_TRAFFIC = {"source_sha256_16": "d33a050e880cdc62", "bytes": 7929.1 * 1024 * 2 + 16.1 * 1024}
 SAD_SOURCE = os.path.join(ROOT, "paper_2508_05990_amd", "csrc", "sad_search.hip")
 
 
@@ -330,7 +330,7 @@ def main():
                                "then %s warp of [256,135,240]" % args.warp_dtype,
                    "frame": [H, W], "block": B, "radius": R, "pairs_per_step": npairs,
                    "features": [256, 135, 240], "warp_dtype": args.warp_dtype, "mode": "exhaustive"},
-        "roofline": {"bound": "alu", "kernel": "sad_search_kernel<16,1,4,4>", "achieved": round(achieved, 3),
+        "roofline": {"bound": "alu", "kernel": "sad_search_kernel<16,1,4,4,false>", "achieved": round(achieved, 3),
                      "peak": round(PEAK_SAD_TOPS, 3), "unit": "TOP/s", "frac": round(achieved / PEAK_SAD_TOPS, 4),
                      "traffic": sad_traffic(), "algorithmic_ops_per_launch": ops},
         "me_ms_per_pair": round(me_avg, 5),
