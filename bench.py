@@ -78,7 +78,10 @@ def cpu_baseline(frames, feats, B, R, budget_s):
 def proposal_leg(me, ctx, frames, mvs_exh, z, outs, B, R, H, W, args):
     """Learned-proposal mode on the same sequence (same GPU, same warp):
     frames/s, MV-error rate against full search (Euclidean error > 1 packed
-    pixel) and fallback rate."""
+    pixel) and fallback rate, for the trained network with the confidence and
+    SAD fallbacks (confidence 0.5, SAD 1.5 x median), for the same network
+    with the SAD fallback only, and for the method without the network (zero
+    proposals, same refine and fallback)."""
     import numpy as np
     import torch
 
@@ -89,35 +92,56 @@ def proposal_leg(me, ctx, frames, mvs_exh, z, outs, B, R, H, W, args):
         return {"skipped": "no weights at %s" % path}
     params, median = train.load_weights(path)
     me.cnn_set_params(ctx, params, median)
-    p = me.make_params(B, R, me.ME_MODE_PROPOSAL, 2, 0.0, 1.5, 0.0)
     npairs = len(frames) - 1
     bh, bw = mvs_exh[0].shape[:2]
     mv = [torch.empty((bh, bw, 2), dtype=torch.int16, device="cuda") for _ in range(npairs)]
     sad = [torch.empty((bh, bw), dtype=torch.int32, device="cuda") for _ in range(npairs)]
     fb = [torch.empty((bh, bw), dtype=torch.uint8, device="cuda") for _ in range(npairs)]
+    zero = torch.zeros((3, bh, bw), dtype=torch.float32, device="cuda")
+    rr = 2
 
-    def step():
+    def run_mode(conf, use_net):
+        p = me.make_params(B, R, me.ME_MODE_PROPOSAL, rr, conf, 1.5, 0.0)
+
+        def step(ev=None):
+            for t in range(npairs):
+                if ev is not None:
+                    ev[t][0].record()
+                if use_net:
+                    me.estimate(frames[t], frames[t + 1], mv=mv[t], sad=sad[t], fallback=fb[t], params=p, ctx=ctx)
+                else:
+                    me.refine(frames[t], frames[t + 1], zero, ctx, B, R, rr, conf, 1.5, median, mv=mv[t],
+                              sad=sad[t], fallback=fb[t])
+                if ev is not None:
+                    ev[t][1].record()
+                me.warp_features(z, mv[t], B, H, W, out=outs[t & 1], ctx=ctx)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(npairs)]
+        step(ev)
+        torch.cuda.synchronize()
+        me_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+        err = fall = 0
         for t in range(npairs):
-            me.estimate(frames[t], frames[t + 1], mv=mv[t], sad=sad[t], fallback=fb[t], params=p, ctx=ctx)
-            me.warp_features(z, mv[t], B, H, W, out=outs[t & 1], ctx=ctx)
+            d = (mv[t].int() - mvs_exh[t].int()).float()
+            err += int(((d[..., 0] ** 2 + d[..., 1] ** 2) > 1.0).sum().item())
+            fall += int(fb[t].sum().item())
+        nb = npairs * bh * bw
+        return {"value": round(npairs * args.steps / wall, 2), "unit": "frames/s", "me_ms_per_pair": round(me_ms, 4),
+                "mv_err_rate": err / nb, "fallback_rate": round(fall / nb, 5)}
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    err = fall = 0
-    for t in range(npairs):
-        d = (mv[t].int() - mvs_exh[t].int()).float()
-        err += int(((d[..., 0] ** 2 + d[..., 1] ** 2) > 1.0).sum().item())
-        fall += int(fb[t].sum().item())
-    nb = npairs * bh * bw
-    return {"value": round(npairs * args.steps / wall, 2), "unit": "frames/s", "mv_err_rate": err / nb,
-            "fallback_rate": fall / nb, "refine_radius": 2, "weights": os.path.relpath(path, ROOT),
-            "ms_per_step": round(wall * 1e3 / args.steps, 4)}
+    res = run_mode(0.0, True)
+    res.update({"refine_radius": rr, "weights": os.path.relpath(path, ROOT), "ms_per_pair": round(1e3 / res["value"], 4)})
+    res["sad_fallback_only"] = run_mode(-1e30, True)
+    res["zero_proposal"] = run_mode(0.0, False)
+    return res
 
 
 def batched_leg(me, ctx, args):

@@ -103,9 +103,10 @@ def build_dataset(me, ctx, n_pairs, seed0, workers, log):
     return X, Y, S, nsamp, median
 
 
-def evaluate(me, ctx, frames, use_net, median, R=32, rr=2):
+def evaluate(me, ctx, frames, use_net, median, R=32, rr=2, conf=0.0):
     """Proposal mode on consecutive pairs: fallback rate, MV-error rate against
-    full search (Euclidean error > 1 packed pixel) and mean time per pair."""
+    full search (Euclidean error > 1 packed pixel) and median time per pair.
+    conf: logit threshold of the confidence fallback (0 = confidence 0.5)."""
     import torch
 
     fb_sum = err_sum = n = 0
@@ -113,7 +114,7 @@ def evaluate(me, ctx, frames, use_net, median, R=32, rr=2):
     net_zero = torch.zeros((3, bh, bw), dtype=torch.float32, device="cuda")
     mv_e = torch.empty((bh, bw, 2), dtype=torch.int16, device="cuda")
     sad_e = torch.empty((bh, bw), dtype=torch.int32, device="cuda")
-    p = me.make_params(16, R, me.ME_MODE_PROPOSAL, rr, 0.0, 1.5, median)
+    p = me.make_params(16, R, me.ME_MODE_PROPOSAL, rr, conf, 1.5, median)
     times = []
     for t in range(1, len(frames)):
         me.estimate(frames[t - 1], frames[t], 16, R, mv=mv_e, sad=sad_e, ctx=ctx)
@@ -123,7 +124,7 @@ def evaluate(me, ctx, frames, use_net, median, R=32, rr=2):
         if use_net:
             mv, sad = me.estimate(frames[t - 1], frames[t], fallback=fb, params=p, ctx=ctx)
         else:
-            mv, sad, fb = me.refine(frames[t - 1], frames[t], net_zero, ctx, 16, R, rr, 0.0, 1.5, median, fallback=fb)
+            mv, sad, fb = me.refine(frames[t - 1], frames[t], net_zero, ctx, 16, R, rr, conf, 1.5, median, fallback=fb)
         b.record()
         torch.cuda.synchronize()
         times.append(a.elapsed_time(b))
@@ -145,6 +146,7 @@ def main(argv=None):
     ap.add_argument("--init-seed", type=int, default=0)
     ap.add_argument("--eval-seed", type=int, default=1, help="held-out 1080p sequence")
     ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--refine-radius", type=int, default=2, help="refine window of the confidence labels")
     ap.add_argument("--mask-ratio", type=float, default=1.5,
                     help="drop the vector term of blocks whose full-search SAD per sample exceeds this multiple "
                          "of the median (0 = keep all)")
@@ -197,7 +199,7 @@ def main(argv=None):
             if wb is not None:
                 torch.index_select(Wt, 0, idx, out=wb)
             lr = cosine_lr(step, total, args.lr, args.lr_min)
-            me.cnn_train_step(ctx, xb, yb, radius=32, refine_radius=2, lr=lr, update=True,
+            me.cnn_train_step(ctx, xb, yb, radius=32, refine_radius=args.refine_radius, lr=lr, update=True,
                               loss=loss if s == steps_per_epoch - 1 else None, weight=wb)
             step += 1
         if ep % 5 == 0 or ep == args.epochs - 1:
@@ -211,10 +213,13 @@ def main(argv=None):
 
     seq = synth.hd_sequence(args.eval_seed)
     frames = [torch.from_numpy(f).cuda() for f in seq.frames]
-    trained = evaluate(me, ctx, frames, True, med)
-    zero = evaluate(me, ctx, frames, False, med)
+    rr = args.refine_radius
+    trained = evaluate(me, ctx, frames, True, med, rr=rr)
+    zero = evaluate(me, ctx, frames, False, med, rr=rr)
+    trained_sad_only = evaluate(me, ctx, frames, True, med, rr=rr, conf=-1e30)
     log({"event": "done", "train_seconds": round(train_s, 1), "total_seconds": round(time.time() - t_all, 1),
-         "steps": total, "weights": args.out, "heldout_trained": trained, "heldout_zero_predictor": zero})
+         "steps": total, "weights": args.out, "refine_radius": rr, "heldout_trained": trained,
+         "heldout_zero_predictor": zero, "heldout_trained_sad_fallback_only": trained_sad_only})
     ctx.close()
     return trained, zero
 

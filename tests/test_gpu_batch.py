@@ -45,7 +45,7 @@ def test_batch_matches_single_launches_and_oracle(dev, oracle_mod):
     try:
         for seed in (0, 1):                  # the second submission replays the captured graph
             jobs = _jobs(dev, seed)
-            print("batch submission", seed, flush=True)   # seed 1: same shapes, cached item list
+            print("batch submission", seed, flush=True)   # seed 1: same shapes, graph replay
             dev.batch_submit(ctx, [(j["t0"], j["t1"], j["B"], j["R"], j["mv"], j["sad"]) for j in jobs])
             torch.cuda.synchronize()
             for k, j in enumerate(jobs):
@@ -75,7 +75,7 @@ def test_batch_of_one_and_reordering(dev):
         for j in rev:
             mv1, sad1 = dev.estimate(j["t0"], j["t1"], j["B"], j["R"])
             assert torch.equal(j["mv"], mv1) and torch.equal(j["sad"], sad1)
-        # fewer items than the tables hold: a rebuilt item list without regrowth
+        # fewer pairs than the pointer table holds: a new graph without regrowth
         j = jobs[1]
         j["mv"].fill_(5)
         j["sad"].fill_(5)
@@ -89,8 +89,9 @@ def test_batch_of_one_and_reordering(dev):
 
 def test_batch_of_mixed_streams(dev):
     """24 streams of four frame sizes up to 3840x2160 and (B, R) in
-    {8, 16} x {16, 32}, one pair each: many items per job, runs of blocks two
-    at a time; bit-identical to one launch per pair, on two submissions."""
+    {8, 16} x {16, 32}, one pair each: shape groups of one to several pairs
+    with partial blocks; bit-identical to one launch per pair, on two
+    submissions (the second replays the graph)."""
     import torch
 
     from paper_2508_05990_amd import synth
