@@ -150,12 +150,21 @@ me_status refine_impl(me_ctx ctx, const me_frame* ref, const me_frame* cur, cons
     if (s != ME_OK) return s;
     uint8_t* fb = fallback ? fallback : ctx->fb;
 
-    hipError_t e = launch_decode(net_out, nblk, p.radius, ctx->pred, st);
-    if (e != hipSuccess) return hip_fail(e, "refine: decode");
-    SearchArgs a = make_args(ref, cur, p.block, p.refine_radius, p.radius, ctx->pred, mv, sad);
-    e = launch_sad_search(a, default_tiles(p.block, p.refine_radius), nblk, st);
-    if (e != hipSuccess) return hip_fail(e, "refine: refine search");
     const double ratio_m = (double)p.sad_ratio * (double)m;
+    hipError_t e;
+    if (small_search(p.block, p.refine_radius)) {
+        // the refine kernel decodes its predictors from the network output
+        SearchArgs a = make_args(ref, cur, p.block, p.refine_radius, p.radius, nullptr, mv, sad);
+        a.net = net_out;
+        e = launch_sad_search(a, default_tiles(p.block, p.refine_radius), nblk, st);
+        if (e != hipSuccess) return hip_fail(e, "refine: refine search");
+    } else {
+        e = launch_decode(net_out, nblk, p.radius, ctx->pred, st);
+        if (e != hipSuccess) return hip_fail(e, "refine: decode");
+        SearchArgs a = make_args(ref, cur, p.block, p.refine_radius, p.radius, ctx->pred, mv, sad);
+        e = launch_sad_search(a, default_tiles(p.block, p.refine_radius), nblk, st);
+        if (e != hipSuccess) return hip_fail(e, "refine: refine search");
+    }
     e = launch_fallback(net_out, sad, bh, bw, Hp, Wp, p.block, p.conf_logit_thresh, ratio_m, fb, ctx->list,
                         ctx->count, st);
     if (e != hipSuccess) return hip_fail(e, "refine: fallback");

@@ -44,6 +44,10 @@ struct SearchArgs {
     // instead of the fields above.  Null for a single pair.
     const JobPtrs* jobs;
     int32_t n_jobs;
+    // proposal refine (small-radius kernel only): predictors decoded from the
+    // network output [3][bh][bw], clamp(rint(8 o), -limit, limit), instead of
+    // `pred`; null otherwise
+    const float* net;
 };
 
 
@@ -67,6 +71,10 @@ TileCfg default_tiles(int B, int R);
 
 // Whether the kernel table has an instance for (B, kx, ky).
 bool tiles_supported(int B, int kx, int ky);
+
+// Whether a search of radius R takes the small-radius kernel (the only one
+// that accepts a.net, the fused proposal decode).
+bool small_search(int B, int R);
 
 // Full or stage search of one pair, of a.n_jobs pairs of one shape
 // (a.jobs), or of the first *a.list_n blocks of a.list (n_wg = list capacity).

@@ -79,6 +79,11 @@ __device__ __forceinline__ void block_geo(const SearchArgs& a, int B, int blk, B
     if (a.pred) {
         px = a.pred[2 * blk];
         py = a.pred[2 * blk + 1];
+    } else if (a.net) {                         // clamp(rint(8 o), -limit, limit), ties to even
+        const float lim = (float)a.limit;
+        const int nblk = a.bh * a.bw;
+        px = (int)fminf(fmaxf(rintf(8.0f * a.net[blk]), -lim), lim);
+        py = (int)fminf(fmaxf(rintf(8.0f * a.net[nblk + blk]), -lim), lim);
     }
     // radius around the predictor, the +-limit box, displaced block in frame
     g.dxlo = max(max(px - a.R, -a.limit), -g.x0);
@@ -503,12 +508,57 @@ __global__ __launch_bounds__(256) void sad_search_generic(SearchArgs a)
     run_generic(a, blk, reinterpret_cast<uint32_t*>(lds_dyn), red);
 }
 
+// SAD of one candidate over rows [r0, r1) of a block of width W words (W = 0:
+// runtime width w), both operands in LDS: cur rows `cp` words apart (the same
+// address in every lane, a broadcast), reference rows `rp` words apart.  The
+// next row's words are requested before the current row is summed.
+template <int W>
+__device__ __forceinline__ uint32_t lds_rows_sad(const uint32_t* cl, int cp, const uint32_t* rl, int rp, int r0,
+                                                 int r1, int w)
+{
+    uint32_t s = 0u;
+    if (W > 0) {
+        if (r0 >= r1) return 0u;
+        uint32_t c[W > 0 ? W : 1], l[W > 0 ? W : 1];
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            c[k] = cl[r0 * cp + k];
+            l[k] = rl[r0 * rp + k];
+        }
+        for (int r = r0; r < r1; ++r) {
+            const int rn = r + 1 < r1 ? r + 1 : r;
+            uint32_t cn[W > 0 ? W : 1], ln[W > 0 ? W : 1];
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                cn[k] = cl[rn * cp + k];
+                ln[k] = rl[rn * rp + k];
+            }
+#pragma unroll
+            for (int k = 0; k < W; ++k) s = __builtin_amdgcn_sad_u16(c[k], l[k], s);
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                c[k] = cn[k];
+                l[k] = ln[k];
+            }
+        }
+    } else {
+        for (int r = r0; r < r1; ++r)
+            for (int k = 0; k < w; ++k) s = __builtin_amdgcn_sad_u16(cl[r * cp + k], rl[r * rp + k], s);
+    }
+    return s;
+}
+
 // Stage searches with a small candidate window (radius <= 4, e.g. the refine
-// step of the proposal path): one wave per block, one candidate per lane, so
-// a 5x5 window keeps 25 lanes busy where a 4x4 tile per lane would keep one.
-// Each wave stages its own block's window in its own LDS slice of
-// a.band_ty words and waits only for its own loads: no workgroup barrier,
-// four independent blocks per workgroup.
+// step of the proposal path): one wave per block, so a 5x5 window keeps most
+// lanes busy where a 4x4 tile per lane would keep one.  Each wave stages its
+// block's reference window and the block itself in its own LDS slice of
+// a.band_ty words and waits only for its own loads (no workgroup barrier,
+// four independent blocks per workgroup).  Lanes are (candidate, row slice)
+// pairs: with nc candidates the block's rows are cut into S slices, the
+// largest power of two with S * nc <= 64, and the slices' partial SADs are
+// added with a butterfly.
+// With a.net (the proposal path), the predictor of each block is decoded
+// from the network output in place.
 template <int CW, int NCH, bool BATCH>
 __global__ __launch_bounds__(256) void sad_small_kernel(SearchArgs a_in)
 {
@@ -538,17 +588,36 @@ __global__ __launch_bounds__(256) void sad_small_kernel(SearchArgs a_in)
     uint64_t best = ~0ull;
     if (g.dxlo <= g.dxhi && g.dylo <= g.dyhi) {
         const int nx = g.dxhi - g.dxlo + 1, ny = g.dyhi - g.dylo + 1;
+        const int nc = nx * ny, rows = 2 * g.h;
         uint32_t* win = reinterpret_cast<uint32_t*>(lds_dyn) + wave * a.band_ty;
+        uint32_t* cblk = win + 2 * (B + 2 * a.R) * a.lds_pitch;        // 2B rows of B words
         stage_window(a, win, 2LL * (g.y0 + g.dylo), g.x0 + g.dxlo, 2 * (g.h + ny - 1), 0, 1, lane);
+        {
+            const int64_t c0 = 2LL * g.y0 * a.cur_pitch + g.x0;
+            for (int r = 0; r < rows; ++r)
+                if (lane < g.w) __builtin_amdgcn_global_load_lds(a.cur + c0 + r * a.cur_pitch + lane, cblk + r * B, 4, 0, 0);
+        }
         __builtin_amdgcn_s_waitcnt(0);
-        cptr_t curp = as_const(a.cur + 2LL * g.y0 * a.cur_pitch + g.x0);
-        for (int cand = lane; cand < nx * ny; cand += 64) {
-            const int cy = cand / nx, cx = cand - cy * nx;
-            const uint32_t* lb = win + 2 * cy * a.lds_pitch + cx;
-            const uint32_t sad = g.w == B ? single_sad_full<CW>(curp, a.cur_pitch, 2 * g.h, NCH, lb, a.lds_pitch)
-                                          : single_sad(curp, a.cur_pitch, 2 * g.h, g.w, lb, a.lds_pitch);
-            const uint64_t key = make_key(sad, g.dxlo + cx, g.dylo + cy);
-            best = key < best ? key : best;
+        int S = 1;
+        while (S < 64 && 2 * S * nc <= 64) S *= 2;
+        const int stride = 64 / S;
+        const int slice = lane / stride, c0 = lane - slice * stride;
+        const int r0 = slice * rows / S, r1 = (slice + 1) * rows / S;
+        for (int base = 0; base < nc; base += stride) {
+            const int cand = base + c0;
+            uint32_t part = 0u;
+            if (cand < nc) {
+                const int cy = cand / nx, cx = cand - cy * nx;
+                const uint32_t* rl = win + 2 * cy * a.lds_pitch + cx;
+                part = g.w == B ? lds_rows_sad<B>(cblk, B, rl, a.lds_pitch, r0, r1, B)
+                                : lds_rows_sad<0>(cblk, B, rl, a.lds_pitch, r0, r1, g.w);
+            }
+            for (int off = stride; off < 64; off <<= 1) part += __shfl_xor(part, off, 64);
+            if (cand < nc && slice == 0) {
+                const int cy = cand / nx, cx = cand - cy * nx;
+                const uint64_t key = make_key(part, g.dxlo + cx, g.dylo + cy);
+                best = key < best ? key : best;
+            }
         }
     }
     best = wave_min_u64(best);
@@ -655,19 +724,25 @@ TileCfg default_tiles(int B, int R)
     return c;
 }
 
-// Window of the small-radius kernel: rows of w + 2R words (a multiple of 4)
-// and its bytes per wave; used for radius <= 4 while a wave's slice fits in
-// 32 KB.
+// LDS slice per wave of the small-radius kernel: the window (rows of B + 2R
+// words, rounded to a multiple of 4) and the current block (2B rows of B
+// words); used for radius <= 4 while the slice fits in 32 KB.
 bool small_plan(int B, int R, int* pitch, int* words)
 {
     if (R > 4) return false;
     const int n = 2 * R + 1;
     const int p = ((B + n - 1) + 3) & ~3;
-    const int w = 2 * (B + n - 1) * p;
+    const int w = 2 * (B + n - 1) * p + 2 * B * B;  // window, then the current block
     if (p > kMaxPitch || (size_t)w * 4 > 32 * 1024) return false;
     *pitch = p;
     *words = w;
     return true;
+}
+
+bool small_search(int B, int R)
+{
+    int p = 0, w = 0;
+    return small_plan(B, R, &p, &w);
 }
 
 template <bool BATCH>
@@ -703,6 +778,7 @@ hipError_t launch_sad_search(const SearchArgs& a, const TileCfg& cfg_in, int n_w
         hipLaunchKernelGGL(sk, dim3((unsigned)((nblk + 3) / 4)), dim3(256), bytes, stream, b);
         return hipGetLastError();
     }
+    if (a.net) return hipErrorInvalidValue;          // decoded predictors: small-radius kernel only
     TileCfg cfg = cfg_in;
     if ((a.list || a.pred || (a.R % 4) != 0) && cfg.nb != 1) {   // one block per workgroup
         cfg.nb = 1;
