@@ -131,6 +131,48 @@ def full_search(ref, cur, B, R, blocks=None, nthreads=0):
     return mv, sad, ov.value
 
 
+# Preset of the paper's FME settings table, "Standard" row: blocks of 64 and
+# 32 Bayer pixels (32 and 16 packed pixels), stages (range, step) coarse
+# (8, 8), intermediate (4, 4), fine (2, 1).
+PYRAMID_BLOCKS = (32, 16)
+PYRAMID_STAGES = ((8, 8), (4, 4), (2, 1))
+
+
+def pyramid_search(ref, cur, blocks=PYRAMID_BLOCKS, stages=PYRAMID_STAGES, limit=127, nthreads=0):
+    """Coarse-to-fine block matching over a block pyramid (paper Sec. 3.2,
+    "Pyramid Block Structure" and "Parallel Coarse-to-fine Block Matching").
+
+    Levels go from the largest block to the smallest; each level runs the
+    stages in order (coarse, intermediate, fine), each stage a stage search
+    around the previous stage's vectors.  The first stage of the first level
+    starts from zero; the first stage of a finer level starts from the vector
+    of the coarser block containing each block.  Every candidate keeps
+    |dx|, |dy| <= limit.  Returns ``(mv, sad, ops_valid, ops_enum)`` for the
+    finest level; the op counts sum over all levels and stages.
+    """
+    rp, cp = pack_planes(ref), pack_planes(cur)
+    _, Hp, Wp = cp.shape
+    mv = None
+    prev_B = None
+    ops_v = ops_e = 0
+    for B in blocks:
+        bh, bw = block_grid(Hp, Wp, B)
+        if mv is None:
+            pred = np.zeros((bh, bw, 2), np.int16)
+        else:
+            r = prev_B // B
+            if r * B != prev_B:
+                raise ValueError("each level's block size must divide the previous one's")
+            pred = mv[np.arange(bh)[:, None] // r, np.arange(bw)[None, :] // r]
+        for R, step in stages:
+            mv, sad, ov, oe = stage_search(rp, cp, B, R, step, pred=pred, limit=limit, nthreads=nthreads)
+            ops_v += ov
+            ops_e += oe
+            pred = mv
+        prev_B = B
+    return mv, sad, ops_v, ops_e
+
+
 def warp_features(z_ref, mv, block, Hp, Wp):
     """Bilinear propagation of a reference feature map by block motion vectors.
 

@@ -40,3 +40,28 @@ def brute_stage(ref, cur, B, R, step=1, pred=None, limit=None):
                         best = key
             out[(bi, bj)] = None if best is None else (best[3], best[2], best[0])
     return out
+
+
+def brute_pyramid(ref, cur, blocks, stages, limit):
+    """Coarse-to-fine search by hand: for each block size from the largest,
+    each (range, step) stage searches around the previous stage's vector; a
+    finer level's first stage starts from the vector of the block of the
+    previous level that contains it (block index // ratio)."""
+    H, W = len(cur), len(cur[0])
+    vec = None
+    prevB = None
+    res = None
+    for B in blocks:
+        bh = (H // 2 + B - 1) // B
+        bw = (W // 2 + B - 1) // B
+        if vec is None:
+            pred = [[(0, 0) for _ in range(bw)] for _ in range(bh)]
+        else:
+            r = prevB // B
+            pred = [[vec[(bi // r, bj // r)] for bj in range(bw)] for bi in range(bh)]
+        for R, step in stages:
+            res = brute_stage(ref, cur, B, R, step, pred, limit)
+            vec = {k: (v[0], v[1]) if v is not None else (0, 0) for k, v in res.items()}
+            pred = [[vec[(bi, bj)] for bj in range(bw)] for bi in range(bh)]
+        prevB = B
+    return res

@@ -250,3 +250,92 @@ def test_block_list_subset(oracle_mod):
     assert np.array_equal(sad.ravel()[idx], sad2.ravel()[idx])
     rest = np.setdiff1d(np.arange(64), idx)
     assert (sad2.ravel()[rest] == -1).all()
+
+
+# --- coarse-to-fine pyramid (paper Sec. 3.2) --------------------------------
+
+@pytest.mark.parametrize("seed", range(4))
+def test_pyramid_matches_brute_force(oracle_mod, seed):
+    """The oracle's pyramid driver against the hand-written one on tiny
+    frames: two levels (block sizes 4 and 2), three strided stages."""
+    from tests.brute import brute_pyramid
+
+    rng = np.random.default_rng(300 + seed)
+    H, W = 2 * int(rng.integers(6, 11)), 2 * int(rng.integers(6, 11))
+    lowent = bool(seed % 2)
+    ref = _rand_mosaic(rng, H, W, lowent)
+    cur = _rand_mosaic(rng, H, W, lowent)
+    stages = ((2, 2), (1, 1))
+    limit = int(rng.integers(2, 6))
+    mv, sad, _, _ = oracle_mod.pyramid_search(ref, cur, blocks=(4, 2), stages=stages, limit=limit, nthreads=1)
+    bf = brute_pyramid(ref.tolist(), cur.tolist(), (4, 2), stages, limit)
+    for (bi, bj), res in bf.items():
+        assert res is not None
+        assert (int(mv[bi, bj, 0]), int(mv[bi, bj, 1]), int(sad[bi, bj])) == res, (bi, bj)
+
+
+@pytest.mark.parametrize("row", _read_settings(), ids=lambda r: r[0])
+def test_pyramid_op_count_reproduces_paper_gflops(oracle_mod, row):
+    """The pyramid driver enumerates, per level, (2R+1)^2 candidates of every
+    stage for every sample: its count scaled to 1024x2048 reproduces the
+    paper's GFLOPs column (Modes 5/6 excepted, as for the stage counts)."""
+    name, stages, blocks, gflops = row
+    H, W = 64, 128
+    rng = np.random.default_rng(2)
+    f = _rand_mosaic(rng, H, W)
+    _, _, _, ops_enum = oracle_mod.pyramid_search(f, f, blocks=tuple(b // 2 for b in blocks), stages=stages,
+                                                  nthreads=2)
+    g = ops_enum * (1024 * 2048) / (H * W) / 1e9
+    if name in ("Mode5", "Mode6"):
+        assert abs(g - 1.422) < 0.005
+    else:
+        assert abs(g - gflops) <= 0.006 * gflops + 0.005, (name, g, gflops)
+
+
+def _smooth_mosaic(rng, Hp, Wp):
+    """RGGB mosaic of four smooth textures (amplitude ~ 1/f^2): their SAD
+    grows monotonically with the misalignment over tens of pixels."""
+    planes = []
+    for _ in range(4):
+        F = np.fft.rfft2(rng.standard_normal((Hp, Wp)))
+        f = np.sqrt(np.fft.fftfreq(Hp)[:, None] ** 2 + np.fft.rfftfreq(Wp)[None, :] ** 2)
+        t = np.fft.irfft2(F / np.maximum(f, 1.0 / max(Hp, Wp)) ** 2, s=(Hp, Wp))
+        planes.append(2048.0 + 512.0 * (t - t.mean()) / t.std())
+    m = np.empty((2 * Hp, 2 * Wp))
+    m[0::2, 0::2], m[0::2, 1::2], m[1::2, 0::2], m[1::2, 1::2] = planes
+    return np.clip(np.rint(m), 0, 4095).astype(np.uint16)
+
+
+@pytest.mark.parametrize("shift", [(-20, 13), (7, -30), (0, 0), (45, 3), (-16, 24)])
+def test_pyramid_recovers_global_shift(oracle_mod, shift):
+    """A smooth frame translated by an integer packed shift within the
+    pyramid's reach (coarse 8x8, intermediate 4x4, fine 2x1: up to 82) is
+    recovered exactly by every block whose displaced block stays inside the
+    frame, with SAD 0 (no noise)."""
+    sx, sy = shift
+    rng = np.random.default_rng(5)
+    Hp, Wp = 160, 224
+    big = _smooth_mosaic(rng, Hp + 128, Wp + 128)
+    oy, ox = 64, 64
+    cur = np.ascontiguousarray(big[2 * oy:2 * (oy + Hp), 2 * ox:2 * (ox + Wp)])
+    # ref content at position p + d equals cur content at p: ref = cur shifted by d
+    ref = np.ascontiguousarray(big[2 * (oy - sy):2 * (oy - sy + Hp), 2 * (ox - sx):2 * (ox - sx + Wp)])
+    mv, sad, _, _ = oracle_mod.pyramid_search(ref, cur, nthreads=4)
+    B = 16
+    ok = 0
+    for bi in range(mv.shape[0]):
+        for bj in range(mv.shape[1]):
+            y0, x0 = bi * B, bj * B
+            if 0 <= y0 + sy and y0 + B + sy <= Hp and 0 <= x0 + sx and x0 + B + sx <= Wp:
+                assert (int(mv[bi, bj, 0]), int(mv[bi, bj, 1])) == (sx, sy) and sad[bi, bj] == 0, (bi, bj, mv[bi, bj])
+                ok += 1
+    assert ok >= 10
+
+
+def test_pyramid_single_level_single_stage_is_full_search(oracle_mod):
+    from paper_2508_05990_amd import synth
+
+    f0, f1, _ = synth.small_pair(2)
+    mv, sad, _, _ = oracle_mod.pyramid_search(f0, f1, blocks=(16,), stages=((8, 1),), limit=8, nthreads=2)
+    mv_f, sad_f, _ = oracle_mod.full_search(f0, f1, 16, 8, nthreads=2)
+    assert np.array_equal(mv, mv_f) and np.array_equal(sad, sad_f)
