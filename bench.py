@@ -144,6 +144,52 @@ def proposal_leg(me, ctx, frames, mvs_exh, z, outs, B, R, H, W, args):
     return res
 
 
+def pyramid_leg(me, ctx, frames, mvs_exh, z, outs, B, R, H, W, args):
+    """The paper's coarse-to-fine pyramid search (Sec. 3.2; standard setting:
+    blocks 32 and 16, stages (8, 8), (4, 4), (2, 1)), candidates limited to
+    the exhaustive radius so that its vectors are comparable: frames/s with
+    the same warp, ME time per pair, MV-error rate against full search."""
+    import numpy as np
+    import torch
+
+    cfg = me.pyramid_cfg((2 * B, B), ((8, 8), (4, 4), (2, 1)), R)
+    npairs = len(frames) - 1
+    bh, bw = mvs_exh[0].shape[:2]
+    mv = [torch.empty((bh, bw, 2), dtype=torch.int16, device="cuda") for _ in range(npairs)]
+    sad = [torch.empty((bh, bw), dtype=torch.int32, device="cuda") for _ in range(npairs)]
+
+    def step(ev=None):
+        for t in range(npairs):
+            if ev is not None:
+                ev[t][0].record()
+            me.pyramid(frames[t], frames[t + 1], ctx, cfg, mv=mv[t], sad=sad[t])
+            if ev is not None:
+                ev[t][1].record()
+            me.warp_features(z, mv[t], B, H, W, out=outs[t & 1], ctx=ctx)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(npairs)]
+    step(ev)
+    torch.cuda.synchronize()
+    me_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    err = 0
+    for t in range(npairs):
+        d = (mv[t].int() - mvs_exh[t].int()).float()
+        err += int(((d[..., 0] ** 2 + d[..., 1] ** 2) > 1.0).sum().item())
+    # enumerated candidates x samples, as the paper's op count: levels x stages x (2R+1)^2 x Hp x Wp x 4
+    ops = 2 * sum((2 * r + 1) ** 2 for r in (8, 4, 2)) * (H // 2) * (W // 2) * 4
+    return {"value": round(npairs * args.steps / wall, 2), "unit": "frames/s", "me_ms_per_pair": round(me_ms, 4),
+            "mv_err_rate": err / (npairs * bh * bw), "setting": "blocks 32,16; stages (8,8),(4,4),(2,1); limit %d" % R,
+            "enumerated_sad_ops_per_pair": ops}
+
+
 def batched_leg(me, ctx, args):
     """24 independent streams of 8 frames (640x480 to 3840x2160, (B, R) in
     {8, 16} x {16, 32}): 168 pairs as one graph-captured persistent launch
@@ -262,6 +308,7 @@ def main():
     ap.add_argument("--no-proposal", action="store_true", help="skip the learned-proposal measurement")
     ap.add_argument("--weights", default=None, help="proposal-network weights (default: the packaged file)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 24-stream batched measurement")
+    ap.add_argument("--no-pyramid", action="store_true", help="skip the pyramid-search measurement")
     ap.add_argument("--uhd-frames", type=int, default=16, help="frames of the 4K sequence (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes (reference for HBM byte counters)")
@@ -364,6 +411,8 @@ def main():
     }
     if not args.no_proposal:
         res["proposal"] = proposal_leg(me, ctx, frames, mvs, z, outs, B, R, H, W, args)
+    if not args.no_pyramid:
+        res["pyramid"] = pyramid_leg(me, ctx, frames, mvs, z, outs, B, R, H, W, args)
     if not args.no_batched:
         res["batched_streams"] = batched_leg(me, ctx, args)
     if args.uhd_frames > 1:

@@ -115,17 +115,50 @@ me_status me_estimate(me_ctx ctx, const me_frame* ref, const me_frame* cur, cons
 /*
  * me_stage_search -- one block-matching stage around per-block predictors
  * (paper Sec. 3.2: one matching stage evaluates a set of candidates per
- * block with one thread group per block).  Candidates are p + (u, v) with
+ * block with one thread group per block; its coarse, intermediate and fine
+ * stages differ in range and step).  Candidates are p + step * (u, v) with
  * u, v in [-radius, radius]; a candidate is kept if the displaced block is
  * inside the reference frame and |dx|, |dy| <= limit.
  *
  * pred : device int16 [bh][bw][2] (dx, dy), or NULL for p = 0.
+ * step : >= 1; step > 1 needs block + 2 radius step <= 256 (ME_E_UNSUPPORTED
+ *        otherwise).
  * limit: 0..127.
  * A block with no valid candidate gets sad = -1 and mv = (0, 0).
  * ctx may be NULL.
  */
 me_status me_stage_search(me_ctx ctx, const me_frame* ref, const me_frame* cur, int32_t block, int32_t radius,
-                          const int16_t* pred, int32_t limit, int16_t* mv, int32_t* sad, void* stream);
+                          int32_t step, const int16_t* pred, int32_t limit, int16_t* mv, int32_t* sad,
+                          void* stream);
+
+/* Block pyramid and stages of me_pyramid. */
+typedef struct {
+    int32_t n_levels;      /* 1..4 */
+    int32_t block[4];      /* packed pixels per level, coarse to fine; each in
+                              {8,16,32,64} and dividing the previous one */
+    int32_t n_stages;      /* 1..4 stages per level */
+    int32_t radius[4];     /* per stage, 0..64 */
+    int32_t step[4];       /* per stage, >= 1 */
+    int32_t limit;         /* |dx|, |dy| <= limit for every candidate, 0..127 */
+} me_pyramid_cfg;
+
+/* The paper's standard setting (FME settings table of Sec. 4): blocks of 64
+ * and 32 Bayer pixels (32 and 16 packed pixels), stages (range, step) =
+ * (8, 8), (4, 4), (2, 1), limit 127. */
+me_pyramid_cfg me_default_pyramid(void);
+
+/*
+ * me_pyramid -- coarse-to-fine block matching over a block pyramid (paper
+ * Sec. 3.2, "Pyramid Block Structure" and "Parallel Coarse-to-fine Block
+ * Matching").  Levels run from the largest block to the smallest; each runs
+ * its stages in order, each a stage search around the previous stage's
+ * vectors; the first stage of the first level starts from zero, that of a
+ * finer level from the vector of the coarser block containing each block.
+ * mv / sad: device [bh][bw] of the finest level's block grid.  Needs a
+ * context (intermediate vectors live in its scratch).
+ */
+me_status me_pyramid(me_ctx ctx, const me_frame* ref, const me_frame* cur, const me_pyramid_cfg* cfg, int16_t* mv,
+                     int32_t* sad, void* stream);
 
 /*
  * me_warp_features -- z_pred = Warp(z_R, MV) (paper Sec. 3.3).

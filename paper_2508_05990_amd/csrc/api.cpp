@@ -80,6 +80,9 @@ SearchArgs make_args(const me_frame* ref, const me_frame* cur, int B, int R, int
     a.R = R;
     a.limit = limit;
     a.pred = pred;
+    a.pred_ratio = 1;
+    a.pred_bw = a.bw;
+    a.step = 1;
     a.mv = mv;
     a.sad = sad;
     return a;
@@ -100,6 +103,9 @@ me_ctx_s::~me_ctx_s()
     if (staged) (void)hipEventDestroy(staged);
     (void)hipFree(ptrs_dev);
     (void)hipHostFree(ptrs_host);
+    (void)hipFree(pyr_mv[0]);
+    (void)hipFree(pyr_mv[1]);
+    (void)hipFree(pyr_sad);
     (void)hipFree(tune_mv);
     (void)hipFree(tune_sad);
 }
@@ -278,18 +284,113 @@ me_status me_estimate(me_ctx ctx, const me_frame* ref, const me_frame* cur, cons
 }
 
 me_status me_stage_search(me_ctx ctx, const me_frame* ref, const me_frame* cur, int32_t block, int32_t radius,
-                          const int16_t* pred, int32_t limit, int16_t* mv, int32_t* sad, void* stream)
+                          int32_t step, const int16_t* pred, int32_t limit, int16_t* mv, int32_t* sad, void* stream)
 {
     me_status s = check_pair(ref, cur);
     if (s != ME_OK) return s;
     if (!mv || !sad) return fail(ME_E_INVAL, "me_stage_search: null mv or sad");
     if (!block_ok(block)) return fail(ME_E_UNSUPPORTED, "me_stage_search: block %d not in {8,16,32,64}", block);
     if (radius < 0 || radius > 64) return fail(ME_E_INVAL, "me_stage_search: radius %d not in [0,64]", radius);
+    if (step < 1 || step > 64) return fail(ME_E_INVAL, "me_stage_search: step %d not in [1,64]", step);
     if (limit < 0 || limit > 127) return fail(ME_E_INVAL, "me_stage_search: limit %d not in [0,127]", limit);
+    if (step > 1 && !step_supported(block, radius, step))
+        return fail(ME_E_UNSUPPORTED, "me_stage_search: window of block %d, radius %d, step %d too wide", block,
+                    radius, step);
     SearchArgs a = make_args(ref, cur, block, radius, limit, pred, mv, sad);
+    a.step = step;
     const TileCfg cfg = tiles_for(ctx, block, radius, a.Hp, a.Wp);
     hipError_t e = launch_sad_search(a, cfg, a.bh * a.bw, reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "me_stage_search: launch");
+    return ME_OK;
+}
+
+me_pyramid_cfg me_default_pyramid(void)
+{
+    me_pyramid_cfg c;
+    memset(&c, 0, sizeof c);
+    c.n_levels = 2;
+    c.block[0] = 32;
+    c.block[1] = 16;
+    c.n_stages = 3;
+    c.radius[0] = 8;
+    c.step[0] = 8;
+    c.radius[1] = 4;
+    c.step[1] = 4;
+    c.radius[2] = 2;
+    c.step[2] = 1;
+    c.limit = 127;
+    return c;
+}
+
+me_status me_pyramid(me_ctx ctx, const me_frame* ref, const me_frame* cur, const me_pyramid_cfg* cfg, int16_t* mv,
+                     int32_t* sad, void* stream)
+{
+    if (!ctx) return fail(ME_E_INVAL, "me_pyramid: null context");
+    if (!cfg) return fail(ME_E_INVAL, "me_pyramid: null configuration");
+    me_status s = check_pair(ref, cur);
+    if (s != ME_OK) return s;
+    if (!mv || !sad) return fail(ME_E_INVAL, "me_pyramid: null mv or sad");
+    const me_pyramid_cfg& c = *cfg;
+    if (c.n_levels < 1 || c.n_levels > 4) return fail(ME_E_INVAL, "me_pyramid: n_levels %d not in [1,4]", c.n_levels);
+    if (c.n_stages < 1 || c.n_stages > 4) return fail(ME_E_INVAL, "me_pyramid: n_stages %d not in [1,4]", c.n_stages);
+    if (c.limit < 0 || c.limit > 127) return fail(ME_E_INVAL, "me_pyramid: limit %d not in [0,127]", c.limit);
+    for (int l = 0; l < c.n_levels; ++l) {
+        if (!block_ok(c.block[l])) return fail(ME_E_UNSUPPORTED, "me_pyramid: block %d not in {8,16,32,64}", c.block[l]);
+        if (l > 0 && c.block[l - 1] % c.block[l])
+            return fail(ME_E_INVAL, "me_pyramid: block %d does not divide %d", c.block[l], c.block[l - 1]);
+    }
+    for (int k = 0; k < c.n_stages; ++k) {
+        if (c.radius[k] < 0 || c.radius[k] > 64) return fail(ME_E_INVAL, "me_pyramid: radius %d not in [0,64]", c.radius[k]);
+        if (c.step[k] < 1 || c.step[k] > 64) return fail(ME_E_INVAL, "me_pyramid: step %d not in [1,64]", c.step[k]);
+        for (int l = 0; l < c.n_levels; ++l)
+            if (c.step[k] > 1 && !step_supported(c.block[l], c.radius[k], c.step[k]))
+                return fail(ME_E_UNSUPPORTED, "me_pyramid: window of block %d, radius %d, step %d too wide",
+                            c.block[l], c.radius[k], c.step[k]);
+    }
+    const int Hp = cur->height / 2, Wp = cur->width / 2;
+    size_t most = 0;
+    for (int l = 0; l < c.n_levels; ++l) {
+        const size_t nb = (size_t)((Hp + c.block[l] - 1) / c.block[l]) * ((Wp + c.block[l] - 1) / c.block[l]);
+        if (nb > most) most = nb;
+    }
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if (most > ctx->pyr_cap) {
+        (void)hipFree(ctx->pyr_mv[0]);
+        (void)hipFree(ctx->pyr_mv[1]);
+        (void)hipFree(ctx->pyr_sad);
+        ctx->pyr_mv[0] = ctx->pyr_mv[1] = nullptr;
+        ctx->pyr_sad = nullptr;
+        ctx->pyr_cap = 0;
+        if (hipMalloc(&ctx->pyr_mv[0], most * 2 * sizeof(int16_t)) != hipSuccess ||
+            hipMalloc(&ctx->pyr_mv[1], most * 2 * sizeof(int16_t)) != hipSuccess ||
+            hipMalloc(&ctx->pyr_sad, most * sizeof(int32_t)) != hipSuccess)
+            return fail(ME_E_NOMEM, "me_pyramid: scratch allocation failed");
+        ctx->pyr_cap = most;
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int16_t* prev = nullptr;      // previous stage's vectors
+    int prev_block = 0, prev_bw = 0;
+    int buf = 0;
+    for (int l = 0; l < c.n_levels; ++l) {
+        for (int k = 0; k < c.n_stages; ++k) {
+            const bool last = l == c.n_levels - 1 && k == c.n_stages - 1;
+            int16_t* out_mv = last ? mv : ctx->pyr_mv[buf];
+            int32_t* out_sad = last ? sad : ctx->pyr_sad;
+            SearchArgs a = make_args(ref, cur, c.block[l], c.radius[k], c.limit, prev, out_mv, out_sad);
+            a.step = c.step[k];
+            if (prev && k == 0) {                   // parent block's vector
+                a.pred_ratio = prev_block / c.block[l];
+                a.pred_bw = prev_bw;
+            }
+            e = launch_sad_search(a, tiles_for(ctx, a.block, a.R, a.Hp, a.Wp), a.bh * a.bw, st);
+            if (e != hipSuccess) return hip_fail(e, "me_pyramid: stage launch");
+            prev = out_mv;
+            prev_block = c.block[l];
+            prev_bw = a.bw;
+            buf ^= 1;
+        }
+    }
     return ME_OK;
 }
 
@@ -500,7 +601,7 @@ me_status me_autotune(me_ctx ctx, const me_frame* ref, const me_frame* cur, int3
     }
     SearchArgs a = make_args(ref, cur, block, radius, radius, nullptr, ctx->tune_mv, ctx->tune_sad);
     const int shapes[6][2] = {{4, 4}, {8, 2}, {4, 2}, {8, 4}, {8, 1}, {4, 1}};
-    const size_t caps[3] = {53 * 1024, 80 * 1024, 160 * 1024};
+    const size_t caps[3] = {53 * 1024, 80 * 1024, 158 * 1024};
     std::vector<TileCfg> cands;
     for (auto& sh : shapes)
         for (int nb : {1, 2}) {

@@ -79,6 +79,10 @@ struct me_ctx_s {
     hipGraphExec_t graph = nullptr;
     std::vector<int64_t> batch_shapes;
     std::vector<int32_t> batch_slot;     // job k -> its row in the pointer table
+    // pyramid search: vectors of the intermediate stages (ping-pong) and SADs
+    int16_t* pyr_mv[2] = {nullptr, nullptr};
+    int32_t* pyr_sad = nullptr;
+    size_t pyr_cap = 0;
     // autotune scratch outputs
     int16_t* tune_mv = nullptr;
     int32_t* tune_sad = nullptr;

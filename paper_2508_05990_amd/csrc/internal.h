@@ -30,7 +30,10 @@ struct SearchArgs {
     int32_t bh, bw;         // block grid
     int32_t R;              // candidates per side around the predictor
     int32_t limit;          // |dx|, |dy| <= limit
-    const int16_t* pred;    // [bh][bw][2] or null (predictor 0)
+    const int16_t* pred;    // [bh/pred_ratio][pred_bw][2] or null (predictor 0)
+    int32_t pred_ratio;     // block (bi, bj) takes the predictor of (bi/ratio, bj/ratio)
+    int32_t pred_bw;        // row length of pred
+    int32_t step;           // candidates p + step * (u, v)
     const int32_t* list;    // optional block list (device); null = all blocks
     const int32_t* list_n;  // device count for `list` (blocks past it exit)
     int16_t* mv;            // [bh][bw][2]
@@ -71,6 +74,9 @@ TileCfg default_tiles(int B, int R);
 
 // Whether the kernel table has an instance for (B, kx, ky).
 bool tiles_supported(int B, int kx, int ky);
+
+// Whether a stage search with step > 1 fits the strided kernel's LDS plan.
+bool step_supported(int B, int R, int step);
 
 // Whether a search of radius R takes the small-radius kernel (the only one
 // that accepts a.net, the fused proposal decode).

@@ -77,8 +77,9 @@ __device__ __forceinline__ void block_geo(const SearchArgs& a, int B, int blk, B
     g.w = min(B, a.Wp - g.x0);
     int px = 0, py = 0;
     if (a.pred) {
-        px = a.pred[2 * blk];
-        py = a.pred[2 * blk + 1];
+        const int pb = a.pred_ratio > 1 ? (bi / a.pred_ratio) * a.pred_bw + bj / a.pred_ratio : blk;
+        px = a.pred[2 * pb];
+        py = a.pred[2 * pb + 1];
     } else if (a.net) {                         // clamp(rint(8 o), -limit, limit), ties to even
         const float lim = (float)a.limit;
         const int nblk = a.bh * a.bw;
@@ -624,6 +625,110 @@ __global__ __launch_bounds__(256) void sad_small_kernel(SearchArgs a_in)
     if (lane == 0) write_result(a, blk, best);
 }
 
+__device__ __forceinline__ int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+// Stage search with step > 1 (the coarse and intermediate stages of the
+// pyramid search, Sec. 3.2): candidates p + step * (u, v), |u|, |v| <= R.
+// One block per workgroup of four waves.  The candidate rows are taken in
+// bands of a.band_ty rows whose reference rows (2 (h + step (rows - 1))
+// mosaic rows of a.lds_pitch words) are staged in LDS.  Each pass deals up
+// to 64 candidates to every group of S waves (S = 4, 2 or 1 as the band has
+// at most 64, 128 or more candidates); the S waves of a group split the
+// block's rows, so each wave's current-block rows stay wave-uniform (scalar
+// loads), and their partial SADs meet in LDS.
+template <int CW, int NCH>
+__global__ __launch_bounds__(256) void sad_step_kernel(SearchArgs a)
+{
+    extern __shared__ uint4 lds_dyn[];
+    __shared__ uint32_t part[256];
+    __shared__ uint64_t red[kMaxWaves];
+    constexpr int B = CW * NCH;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    int blk;
+    if (a.list) {
+        if ((int)blockIdx.x >= *a.list_n) return;     // whole workgroup leaves
+        blk = a.list[blockIdx.x];
+    } else {
+        blk = xcd_remap(blockIdx.x, gridDim.x);
+    }
+    uint32_t* lds = reinterpret_cast<uint32_t*>(lds_dyn);
+    const int s = a.step;
+    const int bi = blk / a.bw, bj = blk - bi * a.bw;
+    const int y0 = bi * B, x0 = bj * B, h = min(B, a.Hp - y0), w = min(B, a.Wp - x0);
+    int px = 0, py = 0;
+    if (a.pred) {
+        const int pb = a.pred_ratio > 1 ? (bi / a.pred_ratio) * a.pred_bw + bj / a.pred_ratio : blk;
+        px = a.pred[2 * pb];
+        py = a.pred[2 * pb + 1];
+    }
+    // u, v such that the displaced block is in the frame and |d| <= limit
+    const int xlo = max(-a.limit, -x0), xhi = min(a.limit, a.Wp - x0 - w);
+    const int ylo = max(-a.limit, -y0), yhi = min(a.limit, a.Hp - y0 - h);
+    const int ulo = max(-a.R, -floor_div(px - xlo, s)), uhi = min(a.R, floor_div(xhi - px, s));
+    const int vlo = max(-a.R, -floor_div(py - ylo, s)), vhi = min(a.R, floor_div(yhi - py, s));
+    uint64_t best = ~0ull;
+    if (ulo <= uhi && vlo <= vhi) {
+        const int nx = uhi - ulo + 1, ny = vhi - vlo + 1;
+        const int pitch = a.lds_pitch;
+        const int gcol = x0 + px + s * ulo;
+        cptr_t curp = as_const(a.cur + 2LL * y0 * a.cur_pitch + x0);
+        for (int cy0 = 0; cy0 < ny; cy0 += a.band_ty) {
+            const int nyb = min(a.band_ty, ny - cy0);
+            __syncthreads();
+            stage_window(a, lds, 2LL * (y0 + py + s * (vlo + cy0)), gcol, 2 * (h + s * (nyb - 1)), wave, 4, lane);
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            const int nc = nx * nyb;
+            const int S = nc <= 64 ? 4 : (nc <= 128 ? 2 : 1);
+            const int per = 64 * (4 / S);
+            const int slice = wave % S, grp = wave / S;
+            const int r0 = slice * 2 * h / S, r1 = (slice + 1) * 2 * h / S;
+            for (int base = 0; base < nc; base += per) {
+                const int cand = base + grp * 64 + lane;
+                const int cy = cand / nx, cx = cand - cy * nx;
+                uint32_t sd = 0u;
+                if (cand < nc) {
+                    const uint32_t* lb = lds + 2 * s * cy * pitch + s * cx;
+                    if (w == B) {
+                        for (int r = r0; r < r1; ++r) {
+                            cptr_t crow = curp + r * a.cur_pitch;
+                            const uint32_t* lrow = lb + r * pitch;
+#pragma unroll
+                            for (int k = 0; k < B; ++k) sd = __builtin_amdgcn_sad_u16(crow[k], lrow[k], sd);
+                        }
+                    } else {
+                        for (int r = r0; r < r1; ++r) {
+                            cptr_t crow = curp + r * a.cur_pitch;
+                            const uint32_t* lrow = lb + r * pitch;
+                            for (int k = 0; k < w; ++k) sd = __builtin_amdgcn_sad_u16(crow[k], lrow[k], sd);
+                        }
+                    }
+                }
+                if (S > 1) {
+                    part[tid] = sd;
+                    __syncthreads();
+                    if (slice == 0)
+                        for (int j = 1; j < S; ++j) sd += part[tid + 64 * j];
+                    __syncthreads();
+                }
+                if (slice == 0 && cand < nc) {
+                    const uint64_t key = make_key(sd, px + s * (ulo + cx), py + s * (vlo + cy0 + cy));
+                    best = key < best ? key : best;
+                }
+            }
+        }
+    }
+    best = wave_min_u64(best);
+    if (lane == 0) red[wave] = best;
+    __syncthreads();
+    if (tid == 0) {
+        uint64_t b = red[0];
+        for (int k = 1; k < 4; ++k) b = red[k] < b ? red[k] : b;
+        write_result(a, blk, b);
+    }
+}
+
 using KernelFn = void (*)(SearchArgs);
 
 template <int CW, int NCH, bool BATCH>
@@ -652,7 +757,7 @@ KernelFn kernel_for(int B, int kx, int ky)
 
 constexpr size_t kLdsCap = 53 * 1024;    // preferred: 3 workgroups per CU
 constexpr size_t kLdsMid = 80 * 1024;    // 2 workgroups per CU
-constexpr size_t kLdsMax = 160 * 1024;   // gfx950 LDS per workgroup
+constexpr size_t kLdsMax = 158 * 1024;   // gfx950 LDS per workgroup (160 KB) less room for static LDS
 
 hipError_t set_lds(const void* k, size_t bytes)
 {
@@ -757,11 +862,68 @@ KernelFn small_kernel_for(int B)
     }
 }
 
+KernelFn step_kernel_for(int B)
+{
+    switch (B) {
+    case 8: return sad_step_kernel<8, 1>;
+    case 16: return sad_step_kernel<16, 1>;
+    case 32: return sad_step_kernel<16, 2>;
+    case 64: return sad_step_kernel<16, 4>;
+    default: return nullptr;
+    }
+}
+
+// Strided stage search: window rows of B + 2 R step words (a multiple of 4,
+// at most kMaxPitch) and the largest band of candidate rows within 64 KB of
+// LDS (160 KB if one row needs more).
+bool step_plan(int B, int R, int step, int* pitch, int* band, size_t* bytes)
+{
+    const int p = ((B + 2 * R * step) + 3) & ~3;
+    if (p > kMaxPitch) return false;
+    const int n = 2 * R + 1;
+    for (size_t cap : {kLdsCap + 11 * 1024, kLdsMax}) {
+        int nyb = n;
+        while (nyb > 1 && (size_t)2 * (B + step * (nyb - 1)) * p * 4 > cap) --nyb;
+        const size_t by = (size_t)2 * (B + step * (nyb - 1)) * p * 4;
+        if (by <= cap) {
+            *pitch = p;
+            *band = nyb;
+            *bytes = by;
+            return true;
+        }
+    }
+    return false;
+}
+
+bool step_supported(int B, int R, int step)
+{
+    int p = 0, nyb = 0;
+    size_t by = 0;
+    return step_plan(B, R, step, &p, &nyb, &by);
+}
+
 hipError_t launch_sad_search(const SearchArgs& a, const TileCfg& cfg_in, int n_wg, hipStream_t stream)
 {
     const bool batch = a.jobs != nullptr;
     const int64_t njobs = batch ? a.n_jobs : 1;
     if (batch && (a.list || a.n_jobs < 1)) return hipErrorInvalidValue;
+    if (a.step < 1) return hipErrorInvalidValue;
+    if (a.step > 1) {
+        if (batch || a.net) return hipErrorInvalidValue;
+        int pitch = 0, nyb = 0;
+        size_t bytes = 0;
+        KernelFn k = step_kernel_for(a.block);
+        if (!k || !step_plan(a.block, a.R, a.step, &pitch, &nyb, &bytes)) return hipErrorInvalidValue;
+        hipError_t e = set_lds(reinterpret_cast<const void*>(k), bytes);
+        if (e != hipSuccess) return e;
+        SearchArgs b = a;
+        b.lds_pitch = pitch;
+        b.band_ty = nyb;
+        const int nw = a.list ? n_wg : a.bh * a.bw;
+        if (nw <= 0) return hipSuccess;
+        hipLaunchKernelGGL(k, dim3(nw), dim3(256), bytes, stream, b);
+        return hipGetLastError();
+    }
     int spitch = 0, swords = 0;
     if (small_plan(a.block, a.R, &spitch, &swords)) {
         KernelFn sk = batch ? small_kernel_for<true>(a.block) : small_kernel_for<false>(a.block);

@@ -58,8 +58,18 @@ _me_ctx_create = _sig("me_ctx_create", [_I32, ctypes.POINTER(_P)])
 _me_ctx_destroy = _sig("me_ctx_destroy", [_P])
 _me_estimate = _sig("me_estimate", [_P, ctypes.POINTER(MeFrame), ctypes.POINTER(MeFrame), ctypes.POINTER(MeParams),
                                     _P, _P, _P, _P])
-_me_stage_search = _sig("me_stage_search", [_P, ctypes.POINTER(MeFrame), ctypes.POINTER(MeFrame), _I32, _I32, _P,
-                                            _I32, _P, _P, _P])
+_me_stage_search = _sig("me_stage_search", [_P, ctypes.POINTER(MeFrame), ctypes.POINTER(MeFrame), _I32, _I32, _I32,
+                                            _P, _I32, _P, _P, _P])
+
+
+class MePyramidCfg(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int32), ("block", ctypes.c_int32 * 4), ("n_stages", ctypes.c_int32),
+                ("radius", ctypes.c_int32 * 4), ("step", ctypes.c_int32 * 4), ("limit", ctypes.c_int32)]
+
+
+_me_default_pyramid = _sig("me_default_pyramid", [], MePyramidCfg)
+_me_pyramid = _sig("me_pyramid", [_P, ctypes.POINTER(MeFrame), ctypes.POINTER(MeFrame), ctypes.POINTER(MePyramidCfg),
+                                  _P, _P, _P])
 _me_warp_features = _sig("me_warp_features", [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _I32, _I32, _I32, _P])
 _me_batch_submit = _sig("me_batch_submit", [_P, ctypes.POINTER(MeJob), _I32, _P])
 _me_refine = _sig("me_refine", [_P, ctypes.POINTER(MeFrame), ctypes.POINTER(MeFrame), ctypes.POINTER(MeParams), _P, _P,
@@ -85,7 +95,8 @@ EXPORTS = ["me_default_params", "me_ctx_create", "me_ctx_destroy", "me_estimate"
            "me_warp_features", "me_batch_submit", "me_refine", "me_status_string", "me_last_error",
            "me_cnn_set_params", "me_cnn_get_params", "me_cnn_pool", "me_cnn_forward", "me_cnn_train_step",
            "me_cnn_state_bytes", "me_cnn_save_state", "me_cnn_load_state", "me_cnn_layer_forward",
-           "me_cnn_layer_backward", "me_cnn_loss", "me_cnn_adamw", "me_autotune"]
+           "me_cnn_layer_backward", "me_cnn_loss", "me_cnn_adamw", "me_autotune", "me_pyramid",
+           "me_default_pyramid"]
 ME_CNN_NPARAMS = 21699
 
 
@@ -175,20 +186,52 @@ def estimate(ref: torch.Tensor, cur: torch.Tensor, block: int = 16, radius: int 
     return mv, sad
 
 
-def stage_search(ref, cur, block, radius, pred=None, limit=None, mv=None, sad=None, ctx=None, stream=None):
-    """One matching stage around per-block predictors (exhaustive when pred is None)."""
+def stage_search(ref, cur, block, radius, pred=None, limit=None, mv=None, sad=None, ctx=None, stream=None, step=1):
+    """One matching stage, candidates pred + step * (u, v), |u|, |v| <= radius
+    (full search when pred is None and step is 1)."""
     H, W = cur.shape
     bh, bw = block_grid(H, W, block)
     if limit is None:
-        limit = radius
+        limit = radius * step
     if mv is None:
         mv = torch.empty((bh, bw, 2), dtype=torch.int16, device=cur.device)
     if sad is None:
         sad = torch.empty((bh, bw), dtype=torch.int32, device=cur.device)
     fr, fc = frame_of(ref), frame_of(cur)
-    _check(_me_stage_search(_ctx_handle(ctx), ctypes.byref(fr), ctypes.byref(fc), block, radius,
+    _check(_me_stage_search(_ctx_handle(ctx), ctypes.byref(fr), ctypes.byref(fc), block, radius, step,
                             None if pred is None else pred.data_ptr(), limit, mv.data_ptr(), sad.data_ptr(),
                             _stream_handle(stream)))
+    return mv, sad
+
+
+def pyramid_cfg(blocks=(32, 16), stages=((8, 8), (4, 4), (2, 1)), limit=127) -> MePyramidCfg:
+    """Block pyramid (coarse to fine) and (radius, step) stages for pyramid()."""
+    c = MePyramidCfg()
+    c.n_levels = len(blocks)
+    for i, b in enumerate(blocks):
+        c.block[i] = b
+    c.n_stages = len(stages)
+    for i, (r, st) in enumerate(stages):
+        c.radius[i] = r
+        c.step[i] = st
+    c.limit = limit
+    return c
+
+
+def pyramid(ref, cur, ctx: Context, cfg: MePyramidCfg | None = None, mv=None, sad=None, stream=None):
+    """Coarse-to-fine pyramid block matching; vectors on the finest level's block grid."""
+    if cfg is None:
+        cfg = _me_default_pyramid()
+    H, W = cur.shape
+    B = cfg.block[cfg.n_levels - 1]
+    bh, bw = block_grid(H, W, B)
+    if mv is None:
+        mv = torch.empty((bh, bw, 2), dtype=torch.int16, device=cur.device)
+    if sad is None:
+        sad = torch.empty((bh, bw), dtype=torch.int32, device=cur.device)
+    fr, fc = frame_of(ref), frame_of(cur)
+    _check(_me_pyramid(ctx.handle, ctypes.byref(fr), ctypes.byref(fc), ctypes.byref(cfg), mv.data_ptr(),
+                       sad.data_ptr(), _stream_handle(stream)))
     return mv, sad
 
 

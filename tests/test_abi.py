@@ -136,9 +136,30 @@ def test_warp_validation(me, case, status):
 
 def test_stage_search_validation(me):
     f = _frame(me)
-    assert me._me_stage_search(None, ctypes.byref(f), ctypes.byref(f), 16, 2, FAKE, 200, FAKE, FAKE, None) == 1
-    assert me._me_stage_search(None, ctypes.byref(f), ctypes.byref(f), 16, 70, None, 8, FAKE, FAKE, None) == 1
-    assert me._me_stage_search(None, ctypes.byref(f), ctypes.byref(f), 4, 2, None, 8, FAKE, FAKE, None) == 2
+    assert me._me_stage_search(None, ctypes.byref(f), ctypes.byref(f), 16, 2, 1, FAKE, 200, FAKE, FAKE, None) == 1
+    assert me._me_stage_search(None, ctypes.byref(f), ctypes.byref(f), 16, 70, 1, None, 8, FAKE, FAKE, None) == 1
+    assert me._me_stage_search(None, ctypes.byref(f), ctypes.byref(f), 4, 2, 1, None, 8, FAKE, FAKE, None) == 2
+    assert me._me_stage_search(None, ctypes.byref(f), ctypes.byref(f), 16, 2, 0, None, 8, FAKE, FAKE, None) == 1
+    # window of 64 + 2 * 8 * 16 words exceeds what the strided kernel stages
+    assert me._me_stage_search(None, ctypes.byref(f), ctypes.byref(f), 64, 8, 16, None, 127, FAKE, FAKE, None) == 2
+
+
+def test_pyramid_defaults_and_validation(me):
+    c = me._me_default_pyramid()
+    assert (c.n_levels, list(c.block[:2]), c.n_stages) == (2, [32, 16], 3)
+    assert [(c.radius[k], c.step[k]) for k in range(3)] == [(8, 8), (4, 4), (2, 1)] and c.limit == 127
+    f = _frame(me)
+    ctx = ctypes.c_void_p(FAKE)
+    assert me._me_pyramid(None, ctypes.byref(f), ctypes.byref(f), ctypes.byref(c), FAKE, FAKE, None) == 1
+    assert me._me_pyramid(ctx, ctypes.byref(f), ctypes.byref(f), None, FAKE, FAKE, None) == 1
+    bad = me.pyramid_cfg(blocks=(16, 32))          # finer block must divide the coarser one
+    assert me._me_pyramid(ctx, ctypes.byref(f), ctypes.byref(f), ctypes.byref(bad), FAKE, FAKE, None) == 1
+    bad = me.pyramid_cfg(limit=128)
+    assert me._me_pyramid(ctx, ctypes.byref(f), ctypes.byref(f), ctypes.byref(bad), FAKE, FAKE, None) == 1
+    bad = me.pyramid_cfg(blocks=(64, 32), stages=((8, 16),))
+    assert me._me_pyramid(ctx, ctypes.byref(f), ctypes.byref(f), ctypes.byref(bad), FAKE, FAKE, None) == 2
+    bad = me.pyramid_cfg(blocks=(32, 12))
+    assert me._me_pyramid(ctx, ctypes.byref(f), ctypes.byref(f), ctypes.byref(bad), FAKE, FAKE, None) == 2
 
 
 def test_batch_validation(me):
