@@ -631,20 +631,21 @@ __device__ __forceinline__ int floor_div(int a, int b) { return a >= 0 ? a / b :
 // pyramid search, Sec. 3.2): candidates p + step * (u, v), |u|, |v| <= R.
 // One block per workgroup of four waves.  The candidate rows are taken in
 // bands of a.band_ty rows whose reference rows (2 (h + step (rows - 1))
-// mosaic rows of a.lds_pitch words) are staged in LDS.  Each pass deals up
-// to 64 candidates to every group of S waves (S = 4, 2 or 1 as the band has
-// at most 64, 128 or more candidates); the S waves of a group split the
-// block's rows, so each wave's current-block rows stay wave-uniform (scalar
-// loads), and their partial SADs meet in LDS.
-template <int CW, int NCH>
+// mosaic rows of a.lds_pitch words) are staged in LDS.  Lanes work word-
+// parallel: a candidate takes B lanes (64 / B candidates per wave), lane k
+// holding word k of every row of the current block in registers and reading
+// word k of the candidate's reference rows -- consecutive words per
+// candidate, so the LDS reads of strided candidates do not pile onto a few
+// banks -- and a butterfly over the B lanes adds the columns up.
+template <int B>
 __global__ __launch_bounds__(256) void sad_step_kernel(SearchArgs a)
 {
     extern __shared__ uint4 lds_dyn[];
-    __shared__ uint32_t part[256];
     __shared__ uint64_t red[kMaxWaves];
-    constexpr int B = CW * NCH;
+    constexpr int G = 64 / B;                       // candidates per wave and pass
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int grp = lane / B, k = lane - grp * B;
     int blk;
     if (a.list) {
         if ((int)blockIdx.x >= *a.list_n) return;     // whole workgroup leaves
@@ -671,8 +672,15 @@ __global__ __launch_bounds__(256) void sad_step_kernel(SearchArgs a)
     if (ulo <= uhi && vlo <= vhi) {
         const int nx = uhi - ulo + 1, ny = vhi - vlo + 1;
         const int pitch = a.lds_pitch;
+        const int rows = 2 * h;
+        // column k of the current block, all rows (0 past the block's width)
+        uint32_t cur[2 * B];
+        {
+            const uint32_t* cp = a.cur + 2LL * y0 * a.cur_pitch + x0 + min(k, w - 1);
+#pragma unroll
+            for (int r = 0; r < 2 * B; ++r) cur[r] = (r < rows && k < w) ? cp[(int64_t)r * a.cur_pitch] : 0u;
+        }
         const int gcol = x0 + px + s * ulo;
-        cptr_t curp = as_const(a.cur + 2LL * y0 * a.cur_pitch + x0);
         for (int cy0 = 0; cy0 < ny; cy0 += a.band_ty) {
             const int nyb = min(a.band_ty, ny - cy0);
             __syncthreads();
@@ -680,39 +688,24 @@ __global__ __launch_bounds__(256) void sad_step_kernel(SearchArgs a)
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
             const int nc = nx * nyb;
-            const int S = nc <= 64 ? 4 : (nc <= 128 ? 2 : 1);
-            const int per = 64 * (4 / S);
-            const int slice = wave % S, grp = wave / S;
-            const int r0 = slice * 2 * h / S, r1 = (slice + 1) * 2 * h / S;
-            for (int base = 0; base < nc; base += per) {
-                const int cand = base + grp * 64 + lane;
-                const int cy = cand / nx, cx = cand - cy * nx;
+            for (int base = 0; base < nc; base += 4 * G) {
+                const int cand = base + wave * G + grp;
+                const int cc = cand < nc ? cand : nc - 1;
+                const int cy = cc / nx, cx = cc - cy * nx;
+                const uint32_t* lb = lds + 2 * s * cy * pitch + s * cx + k;
                 uint32_t sd = 0u;
-                if (cand < nc) {
-                    const uint32_t* lb = lds + 2 * s * cy * pitch + s * cx;
-                    if (w == B) {
-                        for (int r = r0; r < r1; ++r) {
-                            cptr_t crow = curp + r * a.cur_pitch;
-                            const uint32_t* lrow = lb + r * pitch;
+                if (rows == 2 * B) {                    // full height; columns past w hold 0 in cur
 #pragma unroll
-                            for (int k = 0; k < B; ++k) sd = __builtin_amdgcn_sad_u16(crow[k], lrow[k], sd);
-                        }
-                    } else {
-                        for (int r = r0; r < r1; ++r) {
-                            cptr_t crow = curp + r * a.cur_pitch;
-                            const uint32_t* lrow = lb + r * pitch;
-                            for (int k = 0; k < w; ++k) sd = __builtin_amdgcn_sad_u16(crow[k], lrow[k], sd);
-                        }
-                    }
+                    for (int r = 0; r < 2 * B; ++r) sd = __builtin_amdgcn_sad_u16(cur[r], lb[r * pitch], sd);
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 2 * B; ++r)
+                        if (r < rows) sd = __builtin_amdgcn_sad_u16(cur[r], lb[r * pitch], sd);
                 }
-                if (S > 1) {
-                    part[tid] = sd;
-                    __syncthreads();
-                    if (slice == 0)
-                        for (int j = 1; j < S; ++j) sd += part[tid + 64 * j];
-                    __syncthreads();
-                }
-                if (slice == 0 && cand < nc) {
+                if (k >= w) sd = 0u;                    // lanes past the block's width add nothing
+#pragma unroll
+                for (int off = B / 2; off >= 1; off >>= 1) sd += __shfl_xor(sd, off, 64);
+                if (k == 0 && cand < nc) {
                     const uint64_t key = make_key(sd, px + s * (ulo + cx), py + s * (vlo + cy0 + cy));
                     best = key < best ? key : best;
                 }
@@ -724,7 +717,7 @@ __global__ __launch_bounds__(256) void sad_step_kernel(SearchArgs a)
     __syncthreads();
     if (tid == 0) {
         uint64_t b = red[0];
-        for (int k = 1; k < 4; ++k) b = red[k] < b ? red[k] : b;
+        for (int q = 1; q < 4; ++q) b = red[q] < b ? red[q] : b;
         write_result(a, blk, b);
     }
 }
@@ -865,10 +858,10 @@ KernelFn small_kernel_for(int B)
 KernelFn step_kernel_for(int B)
 {
     switch (B) {
-    case 8: return sad_step_kernel<8, 1>;
-    case 16: return sad_step_kernel<16, 1>;
-    case 32: return sad_step_kernel<16, 2>;
-    case 64: return sad_step_kernel<16, 4>;
+    case 8: return sad_step_kernel<8>;
+    case 16: return sad_step_kernel<16>;
+    case 32: return sad_step_kernel<32>;
+    case 64: return sad_step_kernel<64>;
     default: return nullptr;
     }
 }
