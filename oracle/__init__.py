@@ -173,6 +173,32 @@ def pyramid_search(ref, cur, blocks=PYRAMID_BLOCKS, stages=PYRAMID_STAGES, limit
     return mv, sad, ops_v, ops_e
 
 
+def compose_vectors(mv_step, mv_acc, B, Hp, Wp):
+    """Chain block vectors over two frame steps (propagation over a group of
+    pictures, paper Sec. 4.1 test protocol and Sec. 4.4): ``mv_step`` maps
+    the blocks of frame t to frame t-1, ``mv_acc`` the blocks of frame t-1 to
+    the key frame.  Reading: block b of frame t, whose centre is
+    ``(x0 + w // 2, y0 + h // 2)``, lands at centre + mv_step[b] in frame t-1;
+    the block of frame t-1 containing that point (indices clamped to the
+    grid) carries it on to the key frame.  Result: mv_step[b] + mv_acc[b'].
+    int16 [bh, bw, 2] (dx, dy)."""
+    bh, bw = block_grid(Hp, Wp, B)
+    ms = np.asarray(mv_step, dtype=np.int64).reshape(bh, bw, 2)
+    ma = np.asarray(mv_acc, dtype=np.int64).reshape(bh, bw, 2)
+    out = np.empty((bh, bw, 2), np.int64)
+    for bi in range(bh):
+        y0 = bi * B
+        cy = y0 + min(B, Hp - y0) // 2
+        for bj in range(bw):
+            x0 = bj * B
+            cx = x0 + min(B, Wp - x0) // 2
+            px, py = cx + ms[bi, bj, 0], cy + ms[bi, bj, 1]
+            pi = min(max(py // B, 0), bh - 1)
+            pj = min(max(px // B, 0), bw - 1)
+            out[bi, bj] = ms[bi, bj] + ma[pi, pj]
+    return out.astype(np.int16)
+
+
 def warp_features(z_ref, mv, block, Hp, Wp):
     """Bilinear propagation of a reference feature map by block motion vectors.
 

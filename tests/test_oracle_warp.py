@@ -105,3 +105,45 @@ def test_rejects_bad_geometry(oracle_mod):
         oracle_mod.warp_features(z, np.zeros((3, 3, 2), np.int16), 16, 40, 48)   # Hp/Hf != Wp/Wf
     with pytest.raises(ValueError):
         oracle_mod.warp_features(z, np.zeros((3, 3, 2), np.int16), 6, 40, 40)    # s=4 does not divide 6
+
+
+# --- vector composition over a group of pictures ----------------------------
+
+def test_compose_zero_and_identity(oracle_mod):
+    z = np.zeros((5, 7, 2), np.int16)
+    rng = np.random.default_rng(0)
+    acc = rng.integers(-40, 41, (5, 7, 2)).astype(np.int16)
+    assert np.array_equal(oracle_mod.compose_vectors(z, acc, 16, 80, 112), acc)     # no motion: carry as is
+    assert np.array_equal(oracle_mod.compose_vectors(acc * 0, z, 16, 80, 112), z)
+
+
+def test_compose_global_translation(oracle_mod):
+    """Every frame moves by the same d: the chained vector after t steps is
+    t * d for blocks whose chain stays inside the grid."""
+    d = np.array([5, -3], np.int16)
+    bh, bw, B = 8, 10, 16
+    step = np.broadcast_to(d, (bh, bw, 2)).copy()
+    acc = step.copy()
+    for t in range(2, 5):
+        acc = oracle_mod.compose_vectors(step, acc, B, bh * B, bw * B)
+        inner = acc[2:-2, 2:-2]
+        assert (inner == t * d).all()
+
+
+def test_compose_matches_hand_loop(oracle_mod):
+    """Against a loop written from the reading on random vectors, ragged grid."""
+    rng = np.random.default_rng(3)
+    B, Hp, Wp = 8, 45, 61
+    bh, bw = -(-Hp // B), -(-Wp // B)
+    ms = rng.integers(-30, 31, (bh, bw, 2))
+    ma = rng.integers(-99, 100, (bh, bw, 2))
+    got = oracle_mod.compose_vectors(ms, ma, B, Hp, Wp)
+    for bi in range(bh):
+        for bj in range(bw):
+            h = min(B, Hp - bi * B)
+            w = min(B, Wp - bj * B)
+            x = bj * B + w // 2 + int(ms[bi, bj, 0])
+            y = bi * B + h // 2 + int(ms[bi, bj, 1])
+            i = int(np.clip(np.floor(y / B), 0, bh - 1))
+            j = int(np.clip(np.floor(x / B), 0, bw - 1))
+            assert tuple(got[bi, bj]) == (ms[bi, bj, 0] + ma[i, j, 0], ms[bi, bj, 1] + ma[i, j, 1])
