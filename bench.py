@@ -190,6 +190,45 @@ def pyramid_leg(me, ctx, frames, mvs_exh, z, outs, B, R, H, W, args):
             "enumerated_sad_ops_per_pair": ops}
 
 
+def gop_leg(me, ctx, frames, B, R, args):
+    """Propagation over a group of 12 pictures of the 1080p sequence (paper
+    Sec. 4.1 GOP protocol, Sec. 4.4 references) with features that follow the
+    content: the 2x2 mean of each frame's packed planes (4 channels at 1/4 of
+    the Bayer resolution, via the library's pooling kernel).  Per schedule:
+    time per propagated frame (search + chaining + warp) and the mean
+    relative L1 error of the propagated features against the frames' own."""
+    import numpy as np
+    import torch
+
+    from paper_2508_05990_amd import gop
+
+    L = 12
+    fr = frames[:L]
+    H, W = fr[0].shape
+
+    def feat(f):
+        x = me.cnn_pool(ctx, f, f)                          # [H/4, W/4, 8]: ref planes, then cur planes
+        return x[..., 4:].permute(2, 0, 1).float().contiguous()
+
+    truth = [feat(f) for f in fr]
+    out = {"workload": "GOP of 12 frames of the 1080p sequence, B=16 R=32, features [4, 270, 480]"}
+    for sch in gop.SCHEDULES:
+        gop.propagate(ctx, fr, truth[0], sch, B, R)
+        torch.cuda.synchronize()
+        reps = max(1, args.steps // 4)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            feats, _ = gop.propagate(ctx, fr, truth[0], sch, B, R)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / (reps * (L - 1))
+        errs = [float((feats[t - 1] - truth[t]).abs().mean() / truth[t].abs().mean()) for t in range(1, L)]
+        out[sch] = {"ms_per_frame": round(ms, 4), "mean_rel_l1": round(float(np.mean(errs)), 4),
+                    "last_frame_rel_l1": round(errs[-1], 4)}
+    out["no_propagation_rel_l1"] = round(float(np.mean(
+        [float((truth[0] - truth[t]).abs().mean() / truth[t].abs().mean()) for t in range(1, L)])), 4)
+    return out
+
+
 def batched_leg(me, ctx, args):
     """24 independent streams of 8 frames (640x480 to 3840x2160, (B, R) in
     {8, 16} x {16, 32}): 168 pairs as one graph-captured persistent launch
@@ -309,6 +348,7 @@ def main():
     ap.add_argument("--weights", default=None, help="proposal-network weights (default: the packaged file)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 24-stream batched measurement")
     ap.add_argument("--no-pyramid", action="store_true", help="skip the pyramid-search measurement")
+    ap.add_argument("--no-gop", action="store_true", help="skip the group-of-pictures propagation measurement")
     ap.add_argument("--uhd-frames", type=int, default=16, help="frames of the 4K sequence (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes (reference for HBM byte counters)")
@@ -413,6 +453,8 @@ def main():
         res["proposal"] = proposal_leg(me, ctx, frames, mvs, z, outs, B, R, H, W, args)
     if not args.no_pyramid:
         res["pyramid"] = pyramid_leg(me, ctx, frames, mvs, z, outs, B, R, H, W, args)
+    if not args.no_gop:
+        res["gop_propagation"] = gop_leg(me, ctx, frames, B, R, args)
     if not args.no_batched:
         res["batched_streams"] = batched_leg(me, ctx, args)
     if args.uhd_frames > 1:

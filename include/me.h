@@ -180,6 +180,19 @@ me_status me_warp_features(me_ctx ctx, const void* z_ref, void* z_out, int32_t d
                            void* stream);
 
 /*
+ * me_compose_vectors -- chain block vectors over a group of pictures (paper
+ * Sec. 4.1 GOP test protocol; Sec. 4.4 compares references).  mv_step maps the
+ * blocks of frame t to frame t-1, mv_acc_in the blocks of frame t-1 to the key
+ * frame; mv_acc_out[b] = mv_step[b] + mv_acc_in[b'], where b' is the block of
+ * frame t-1 containing block b's centre (x0 + w/2, y0 + h/2) displaced by
+ * mv_step[b] (block indices clamped to the grid).  All device int16
+ * [bh][bw][2] for `block` on a frame_h x frame_w mosaic; sums wrap to int16.
+ * mv_acc_out may alias mv_step but not mv_acc_in.
+ */
+me_status me_compose_vectors(const int16_t* mv_step, const int16_t* mv_acc_in, int16_t* mv_acc_out, int32_t block,
+                             int32_t frame_h, int32_t frame_w, void* stream);
+
+/*
  * me_refine -- refine-and-fallback step of the learned-proposal mode, given
  * the proposal network's per-block output.  The proposal network is this
  * library's addition: the paper's own learned part corrects features

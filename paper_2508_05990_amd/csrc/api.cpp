@@ -426,6 +426,25 @@ me_status me_warp_features(me_ctx ctx, const void* z_ref, void* z_out, int32_t d
     return ME_OK;
 }
 
+me_status me_compose_vectors(const int16_t* mv_step, const int16_t* mv_acc_in, int16_t* mv_acc_out, int32_t block,
+                             int32_t frame_h, int32_t frame_w, void* stream)
+{
+    if (!mv_step || !mv_acc_in || !mv_acc_out) return fail(ME_E_INVAL, "me_compose_vectors: null pointer");
+    if (!block_ok(block)) return fail(ME_E_UNSUPPORTED, "me_compose_vectors: block %d not in {8,16,32,64}", block);
+    if (frame_h < 2 || frame_w < 2 || (frame_h & 1) || (frame_w & 1) || frame_h > 65536 || frame_w > 65536)
+        return fail(ME_E_INVAL, "me_compose_vectors: frame size must be even, 2..65536");
+    const int Hp = frame_h / 2, Wp = frame_w / 2;
+    const int bh = (Hp + block - 1) / block, bw = (Wp + block - 1) / block;
+    const size_t bytes = (size_t)bh * bw * 2 * sizeof(int16_t);
+    const char* o = reinterpret_cast<const char*>(mv_acc_out);
+    const char* a = reinterpret_cast<const char*>(mv_acc_in);
+    if (o < a + bytes && a < o + bytes) return fail(ME_E_INVAL, "me_compose_vectors: mv_acc_out overlaps mv_acc_in");
+    hipError_t e = launch_compose(mv_step, mv_acc_in, mv_acc_out, bh, bw, block, Hp, Wp,
+                                  reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "me_compose_vectors: launch");
+    return ME_OK;
+}
+
 me_status me_refine(me_ctx ctx, const me_frame* ref, const me_frame* cur, const me_params* params,
                     const float* net_out, int16_t* mv, int32_t* sad, uint8_t* fallback, void* stream)
 {

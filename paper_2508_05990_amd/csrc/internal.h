@@ -86,6 +86,10 @@ bool small_search(int B, int R);
 // (a.jobs), or of the first *a.list_n blocks of a.list (n_wg = list capacity).
 hipError_t launch_sad_search(const SearchArgs& a, const TileCfg& cfg, int n_wg, hipStream_t stream);
 
+// Chained block vectors over a group of pictures (out may alias ms).
+hipError_t launch_compose(const int16_t* ms, const int16_t* ma, int16_t* out, int bh, int bw, int B, int Hp, int Wp,
+                          hipStream_t stream);
+
 // Bilinear propagation of a feature map by block vectors.
 hipError_t launch_warp(const void* z, void* out, int bf16, int C, int Hf, int Wf, const int16_t* mv, int bw,
                        int cells, int s, hipStream_t stream);

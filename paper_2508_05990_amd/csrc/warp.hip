@@ -101,7 +101,37 @@ __global__ __launch_bounds__(256) void warp_kernel(const void* __restrict__ zin,
     }
 }
 
+// Chain block vectors over a group of pictures: block b's centre displaced
+// by its step vector falls in block b' of the previous frame, whose vector to
+// the key frame is added.  One thread per block; out may alias ms (each
+// thread reads only its own step vector) but not ma.
+__global__ void compose_kernel(const int16_t* __restrict__ ms, const int16_t* ma, int16_t* out, int bh, int bw,
+                               int B, int Hp, int Wp)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= bh * bw) return;
+    const int bi = b / bw, bj = b - bi * bw;
+    const int h = min(B, Hp - bi * B), w = min(B, Wp - bj * B);
+    const int vx = ms[2 * b], vy = ms[2 * b + 1];
+    const int px = bj * B + w / 2 + vx, py = bi * B + h / 2 + vy;
+    const int fi = py >= 0 ? py / B : -((-py + B - 1) / B);
+    const int fj = px >= 0 ? px / B : -((-px + B - 1) / B);
+    const int pi = min(max(fi, 0), bh - 1), pj = min(max(fj, 0), bw - 1);
+    const int pb = pi * bw + pj;
+    out[2 * b] = (int16_t)(vx + ma[2 * pb]);
+    out[2 * b + 1] = (int16_t)(vy + ma[2 * pb + 1]);
+}
+
 }  // namespace
+
+hipError_t launch_compose(const int16_t* ms, const int16_t* ma, int16_t* out, int bh, int bw, int B, int Hp, int Wp,
+                          hipStream_t stream)
+{
+    const int n = bh * bw;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(compose_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, ms, ma, out, bh, bw, B, Hp, Wp);
+    return hipGetLastError();
+}
 
 hipError_t launch_warp(const void* z, void* out, int bf16, int C, int Hf, int Wf, const int16_t* mv, int bw,
                        int cells, int s, hipStream_t stream)

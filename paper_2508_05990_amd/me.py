@@ -67,6 +67,7 @@ class MePyramidCfg(ctypes.Structure):
                 ("radius", ctypes.c_int32 * 4), ("step", ctypes.c_int32 * 4), ("limit", ctypes.c_int32)]
 
 
+_me_compose_vectors = _sig("me_compose_vectors", [_P, _P, _P, _I32, _I32, _I32, _P])
 _me_default_pyramid = _sig("me_default_pyramid", [], MePyramidCfg)
 _me_pyramid = _sig("me_pyramid", [_P, ctypes.POINTER(MeFrame), ctypes.POINTER(MeFrame), ctypes.POINTER(MePyramidCfg),
                                   _P, _P, _P])
@@ -96,7 +97,7 @@ EXPORTS = ["me_default_params", "me_ctx_create", "me_ctx_destroy", "me_estimate"
            "me_cnn_set_params", "me_cnn_get_params", "me_cnn_pool", "me_cnn_forward", "me_cnn_train_step",
            "me_cnn_state_bytes", "me_cnn_save_state", "me_cnn_load_state", "me_cnn_layer_forward",
            "me_cnn_layer_backward", "me_cnn_loss", "me_cnn_adamw", "me_autotune", "me_pyramid",
-           "me_default_pyramid"]
+           "me_default_pyramid", "me_compose_vectors"]
 ME_CNN_NPARAMS = 21699
 
 
@@ -202,6 +203,16 @@ def stage_search(ref, cur, block, radius, pred=None, limit=None, mv=None, sad=No
                             None if pred is None else pred.data_ptr(), limit, mv.data_ptr(), sad.data_ptr(),
                             _stream_handle(stream)))
     return mv, sad
+
+
+def compose_vectors(mv_step, mv_acc, block, frame_h, frame_w, out=None, stream=None):
+    """Chain block vectors over a group of pictures: frame t -> t-1 (mv_step)
+    then t-1 -> key frame (mv_acc); returns the vectors frame t -> key frame."""
+    if out is None:
+        out = torch.empty_like(mv_step)
+    _check(_me_compose_vectors(mv_step.data_ptr(), mv_acc.data_ptr(), out.data_ptr(), block, frame_h, frame_w,
+                               _stream_handle(stream)))
+    return out
 
 
 def pyramid_cfg(blocks=(32, 16), stages=((8, 8), (4, 4), (2, 1)), limit=127) -> MePyramidCfg:
