@@ -11,7 +11,9 @@ library (it neither imports nor loads it) and is written from the paper:
   ``z_pred = Warp(z_R, MV)`` -- paper Sec. 3.3 (perception-residual
   formulation); implemented here in float64 numpy;
 * the proposal/refine/fallback decisions of the learned-proposal mode, the
-  proposal CNN and its training loss/optimiser (``cnn.py``).
+  proposal CNN and its training loss/optimiser (``cnn.py``);
+* the perception residual network that corrects propagated features, its
+  weighted BerHu loss and its gradients (``prnet.py``, paper Sec. 3.3).
 
 Every function names the passage it follows; the readings taken where the
 paper is silent are listed in the module docstrings.
