@@ -322,6 +322,127 @@ me_status me_batch_submit(me_ctx ctx, const me_job* jobs, int32_t n, void* strea
 me_status me_autotune(me_ctx ctx, const me_frame* ref, const me_frame* cur, int32_t block, int32_t radius,
                       int32_t iters, float* best_ms, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Perception residual network (PRNet, paper Sec. 3.3): corrects propagated
+ * features, z_out = z_pred + r with r = PRNet(current frame, z_pred), trained
+ * on the residual z_C - z_pred with a region-weighted reverse Huber (BerHu)
+ * loss.  The paper gives the parts but no widths; this build's network:
+ *   encoder: two depthwise-separable blocks over the current frame's packed
+ *     planes ((v - 2048) / 1024): depthwise 3x3 stride 2 (+bias, ReLU6), then
+ *     1x1 to c_enc channels (+bias, ReLU6); output on the feature grid
+ *     Hf = ceil(Hp/4), Wf = ceil(Wp/4) (Hp, Wp = packed plane size);
+ *   projection: 1x1 over [z_pred, encoder] to c_hid channels (+bias, ReLU6);
+ *   n_blocks inverted residual blocks: 1x1 to expand*c_hid (+bias, ReLU6),
+ *     depthwise 3x3 stride 1 (+bias, ReLU6), 1x1 back to c_hid (+bias), plus
+ *     the block input;
+ *   head: 1x1 to c_feat channels (+bias): the residual r.
+ * Loss per feature position p (t = z_target - z_pred): p counts as wrongly
+ * propagated when the channel mean of |t| exceeds tau; each of the two
+ * regions carries half the loss (a region that is empty, or tau < 0, gives
+ * the plain mean); the term is BerHu(r - t) / c_feat with threshold
+ * c = 0.2 max |r - t| over the batch (held constant in the gradient).
+ * Parameters are one float32 vector, layer by layer in the order above
+ * (weights then biases; depthwise weights [C][9], tap = 3 ky + kx; 1x1
+ * weights [c_out][c_in]).  Activations are bfloat16 channels-last; 1x1
+ * convolutions run on bfloat16 MFMA with float32 accumulation; depthwise
+ * weights and all biases stay float32.  Features are [n][c_feat][Hf][Wf].
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t c_feat;    /* feature channels, multiple of 16 */
+    int32_t c_enc;     /* encoder channels, multiple of 16 */
+    int32_t c_hid;     /* hidden channels, multiple of 16 */
+    int32_t expand;    /* expansion of the inverted residual blocks, 1..16 */
+    int32_t n_blocks;  /* inverted residual blocks, 0..16 */
+} me_prnet_cfg;        /* widths: c_feat + c_enc + c_hid, expand*c_hid + c_hid <= 1024 */
+
+typedef struct me_prnet_s* me_prnet;
+
+typedef enum { ME_NHWC = 0, ME_NCHW = 1 } me_layout;
+
+/* A device tensor of n images of HW pixels (layer calls): [n][HW][C]
+ * (ME_NHWC) or [n][C][HW] (ME_NCHW); channels a multiple of 4. */
+typedef struct {
+    const void* data;
+    int32_t channels;
+    int32_t layout;    /* me_layout */
+    int32_t dtype;     /* me_dtype */
+} me_tensor;
+
+/* Number of parameters of a configuration, or -1 if it is invalid. */
+int64_t me_prnet_num_params(const me_prnet_cfg* cfg);
+
+/* Create a network on the context's device (parameters unset: ME_E_STATE for
+ * forward/train until me_prnet_set_params).  The network owns its parameters,
+ * AdamW moments, packed operands and an activation workspace grown to the
+ * largest call (growth synchronises the device). */
+me_status me_prnet_create(me_ctx ctx, const me_prnet_cfg* cfg, me_prnet* out);
+me_status me_prnet_destroy(me_prnet net);
+
+/* Parameters from / to HOST memory (synchronous).  Setting them clears the
+ * AdamW moments and step count. */
+me_status me_prnet_set_params(me_prnet net, const float* params, int64_t count);
+me_status me_prnet_get_params(me_prnet net, float* params, int64_t count);
+
+/*
+ * me_prnet_forward -- corrected features of n frames (paper Sec. 3.3):
+ * cur = the first current mosaic (device), frame k at cur->data +
+ * k * frame_stride elements; z_pred, z_out device [n][c_feat][Hf][Wf] in
+ * `dtype` (ME_F32 or ME_BF16; z_out may not alias z_pred).  Asynchronous on
+ * `stream`.  Calls on one network share its workspace: order them.
+ */
+me_status me_prnet_forward(me_prnet net, const me_frame* cur, int32_t n, int64_t frame_stride, const void* z_pred,
+                           void* z_out, int32_t dtype, void* stream);
+
+/*
+ * me_prnet_train_step -- forward, weighted BerHu loss against z_target, backward
+ * (paper Sec. 3.3) and, when update != 0, one AdamW step (beta 0.9, 0.999,
+ * eps 1e-8, weight decay 0.01, decoupled; learning rate lr).  z_pred, z_target:
+ * device float32 [n][c_feat][Hf][Wf]; loss: device float (written); grads:
+ * device float [num_params] or NULL (receives the gradient).  No gradient
+ * flows into z_pred.  Asynchronous on `stream`; results are bit-reproducible.
+ */
+me_status me_prnet_train_step(me_prnet net, const me_frame* cur, int32_t n, int64_t frame_stride, const float* z_pred,
+                              const float* z_target, float tau, float lr, int32_t update, float* grads, float* loss,
+                              void* stream);
+
+/* Single layers (device pointers; scratch in the context, so calls that share a
+ * context must be ordered).  Depthwise 3x3, zero padding 1, stride 1 or 2:
+ * x bfloat16 [n][H][W][C], w float32 [C][9], b float32 [C], y bfloat16
+ * [n][ceil(H/s)][ceil(W/s)][C], ReLU6 when relu6 != 0. */
+me_status me_prnet_dw_forward(me_ctx ctx, const uint16_t* x, const float* w, const float* b, int32_t n, int32_t H,
+                              int32_t W, int32_t C, int32_t stride, int32_t relu6, uint16_t* y, void* stream);
+
+/* Gradients of me_prnet_dw_forward given dy (bfloat16, output shape): dx
+ * (bfloat16 [n][H][W][C], or NULL) times the ReLU6 derivative of `mask` (the
+ * stored input activation, read where 0 < mask < 6; NULL = none), and grads
+ * (float32 [C*9 + C]: weights then bias, or NULL). */
+me_status me_prnet_dw_backward(me_ctx ctx, const uint16_t* x, const float* w, const uint16_t* dy, const uint16_t* mask,
+                               int32_t n, int32_t H, int32_t W, int32_t C, int32_t stride, uint16_t* dx, float* grads,
+                               void* stream);
+
+/* 1x1 convolution over n*HW pixels: input channels = x then x2 (x2 NULL or
+ * x2->data NULL for none); w float32 [cout][cin]; b [cout] or NULL; then
+ * ReLU6 (relu6 != 0), + add (NULL for none), times the ReLU6 derivative of
+ * mask (bfloat16 [n*HW][cout], NULL for none); written to out (cout channels,
+ * any layout and dtype). */
+me_status me_prnet_pw_forward(me_ctx ctx, const me_tensor* x, const me_tensor* x2, int32_t n, int32_t HW,
+                              const float* w, const float* b, int32_t cout, int32_t relu6, const me_tensor* add,
+                              const uint16_t* mask, const me_tensor* out, void* stream);
+
+/* Gradients of a 1x1 convolution given dy (cout channels): grads (float32
+ * [cout*cin + cout], weights then bias, or NULL) and dx (bfloat16 [n*HW]
+ * [dx_count], or NULL) = the gradient of input channels dx_c0 .. dx_c0 +
+ * dx_count - 1, + add (bfloat16, same shape, or NULL), times the ReLU6
+ * derivative of mask (same shape, or NULL). */
+me_status me_prnet_pw_backward(me_ctx ctx, const me_tensor* x, const me_tensor* x2, const me_tensor* dy, int32_t n,
+                               int32_t HW, const float* w, int32_t cout, int32_t dx_c0, int32_t dx_count,
+                               const uint16_t* add, const uint16_t* mask, uint16_t* dx, float* grads, void* stream);
+
+/* The weighted BerHu loss alone: r, z_pred, z_target float32 [n][C][Hf][Wf];
+ * dr (bfloat16, same shape) = dloss/dr; loss: device float. */
+me_status me_prnet_loss(me_ctx ctx, const float* r, const float* z_pred, const float* z_target, int32_t n, int32_t C,
+                        int32_t Hf, int32_t Wf, float tau, uint16_t* dr, float* loss, void* stream);
+
 /* Human-readable name of a status code (static string). */
 const char* me_status_string(me_status s);
 

@@ -108,6 +108,7 @@ me_ctx_s::~me_ctx_s()
     (void)hipFree(pyr_sad);
     (void)hipFree(tune_mv);
     (void)hipFree(tune_sad);
+    (void)hipFree(prn_scratch);
 }
 
 namespace me {

@@ -22,46 +22,11 @@
 // over pixels in LDS-staged chunks into per-workgroup partials that a second
 // kernel sums in a fixed order: no float atomics, so training is
 // bit-reproducible.
+#include "bf16.h"
 #include "internal.h"
 
 namespace me {
 namespace {
-
-typedef short v4i16 __attribute__((ext_vector_type(4)));
-typedef float v4f32 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ float bf2f(uint16_t v) { return __uint_as_float((uint32_t)v << 16); }
-
-__device__ __forceinline__ uint16_t f2bf(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-
-__device__ __forceinline__ v4i16 as_v4(uint2 u)
-{
-    v4i16 r;
-    r.x = (short)(u.x & 0xffff);
-    r.y = (short)(u.x >> 16);
-    r.z = (short)(u.y & 0xffff);
-    r.w = (short)(u.y >> 16);
-    return r;
-}
-
-__device__ __forceinline__ uint2 pack4(float a, float b, float c, float d)
-{
-    uint2 r;
-    r.x = (uint32_t)f2bf(a) | (uint32_t)f2bf(b) << 16;
-    r.y = (uint32_t)f2bf(c) | (uint32_t)f2bf(d) << 16;
-    return r;
-}
-
-__device__ __forceinline__ v4f32 mfma(v4i16 a, v4i16 b, v4f32 c)
-{
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
-}
 
 // ---------------------------------------------------------------- pooling --
 

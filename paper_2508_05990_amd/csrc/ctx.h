@@ -83,6 +83,9 @@ struct me_ctx_s {
     int16_t* pyr_mv[2] = {nullptr, nullptr};
     int32_t* pyr_sad = nullptr;
     size_t pyr_cap = 0;
+    // scratch of the single-layer network calls (packed weights, partials)
+    void* prn_scratch = nullptr;
+    size_t prn_scratch_cap = 0;
     // autotune scratch outputs
     int16_t* tune_mv = nullptr;
     int32_t* tune_sad = nullptr;

@@ -121,6 +121,58 @@ hipError_t launch_conv_wgrad(int l, const uint16_t* x, const uint16_t* dz, float
 hipError_t launch_adamw(float* w, const float* g, float* m, float* v, int np, float lr, float b1, float b2, float eps,
                         float wd, float c1, float c2, hipStream_t st);
 
+// Perception residual network (prnet.hip).  A tensor view: pixel p = (n, y, x)
+// of HW pixels per image, C channels (a multiple of 4), stored [n][HW][C]
+// (chw = 0) or [n][C][HW] (chw = 1), float32 (f32 = 1) or bfloat16.
+struct PwTensor {
+    const void* p;
+    int32_t C, chw, f32;
+};
+
+// 1x1 convolution (or its input gradient) as a GEMM over P pixels: out[p][m]
+// = sum_k A[m][k] x[p][k] with x = [x, x2] along k; then + bias, ReLU6, + add,
+// times the ReLU6 derivative of mask (bfloat16 [P][M]); stored as `out`.
+struct PwArgs {
+    PwTensor x, x2;             // x2.p may be null
+    int32_t HW, P;
+    const uint16_t* w;          // packed A operand, (M/16 rounded up) x KS tiles
+    int32_t M, KS;              // output channels (multiple of 4), K / 16
+    const float* bias;          // [M] or null
+    int32_t relu6;
+    PwTensor add;               // add.p may be null; add.C == M
+    const uint16_t* mask;       // or null
+    void* out;
+    int32_t out_chw, out_f32;
+};
+
+// Weight gradient of a 1x1 convolution: dW[o][c] = sum_p dy[p][o] x[p][c],
+// db[o] = sum_p dy[p][o]; per-workgroup partials (chunk pixels each) then a
+// fixed-order reduction.
+struct PwGradArgs {
+    PwTensor x, x2, dy;
+    int32_t HW, P, cin, cout, chunk;
+    float* partial;             // nwg * (cout * cin + cout) floats
+};
+
+size_t pw_lds_bytes(int KS);
+size_t pw_wgrad_lds_bytes(int cin, int cout);
+int wgrad_chunk(int P, int target_wg);
+hipError_t launch_pw(const PwArgs& a, hipStream_t st);
+hipError_t launch_pw_pack(const float* w, int ld, int m0, int trans, int Mv, int Kv, int MT, int KS, uint16_t* out,
+                          hipStream_t st);
+hipError_t launch_pw_wgrad(const PwGradArgs& a, float* gw, float* gb, hipStream_t st);
+hipError_t launch_dw_fwd(const uint16_t* x, const float* w, const float* b, uint16_t* y, int n, int H, int W, int C,
+                         int S, int relu6, hipStream_t st);
+hipError_t launch_dw_dgrad(const uint16_t* dy, const float* w, const uint16_t* mask, uint16_t* dx, int n, int H, int W,
+                           int C, int S, hipStream_t st);
+hipError_t launch_dw_wgrad(const uint16_t* x, const uint16_t* dy, float* partial, int nwg, int chunk, float* gw,
+                           float* gb, int n, int H, int W, int C, int S, hipStream_t st);
+hipError_t launch_planes(const uint16_t* m, int64_t pitch, int64_t img_stride, int n, int Hp, int Wp, uint16_t* out,
+                         hipStream_t st);
+int prloss_blocks(int P);
+hipError_t launch_prloss(const float* r, const float* zp, const float* zt, int n, int C, int HW, float tau,
+                         int32_t* nbad, uint32_t* maxbits, uint16_t* dr, float* partial, float* loss, hipStream_t st);
+
 hipError_t launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t stream);
 hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t stream);
 

@@ -89,6 +89,34 @@ _me_cnn_layer_forward = _sig("me_cnn_layer_forward", [_P, _I32, _P, _P, _I32, _I
 _me_cnn_layer_backward = _sig("me_cnn_layer_backward", [_P, _I32, _P, _P, _P, _P, _I32, _I32, _I32, _P])
 _me_cnn_loss = _sig("me_cnn_loss", [_P, _P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P])
 _me_cnn_adamw = _sig("me_cnn_adamw", [_P, _P, _F, _P])
+
+
+class MePrnetCfg(ctypes.Structure):
+    _fields_ = [("c_feat", ctypes.c_int32), ("c_enc", ctypes.c_int32), ("c_hid", ctypes.c_int32),
+                ("expand", ctypes.c_int32), ("n_blocks", ctypes.c_int32)]
+
+
+class MeTensor(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("channels", ctypes.c_int32), ("layout", ctypes.c_int32),
+                ("dtype", ctypes.c_int32)]
+
+
+_PT = ctypes.POINTER(MeTensor)
+_I64 = ctypes.c_int64
+_me_prnet_num_params = _sig("me_prnet_num_params", [ctypes.POINTER(MePrnetCfg)], _I64)
+_me_prnet_create = _sig("me_prnet_create", [_P, ctypes.POINTER(MePrnetCfg), ctypes.POINTER(_P)])
+_me_prnet_destroy = _sig("me_prnet_destroy", [_P])
+_me_prnet_set_params = _sig("me_prnet_set_params", [_P, _P, _I64])
+_me_prnet_get_params = _sig("me_prnet_get_params", [_P, _P, _I64])
+_me_prnet_forward = _sig("me_prnet_forward", [_P, ctypes.POINTER(MeFrame), _I32, _I64, _P, _P, _I32, _P])
+_me_prnet_train_step = _sig("me_prnet_train_step", [_P, ctypes.POINTER(MeFrame), _I32, _I64, _P, _P, _F, _F, _I32,
+                                                    _P, _P, _P])
+_me_prnet_dw_forward = _sig("me_prnet_dw_forward", [_P, _P, _P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P])
+_me_prnet_dw_backward = _sig("me_prnet_dw_backward", [_P, _P, _P, _P, _P, _I32, _I32, _I32, _I32, _I32, _P, _P, _P])
+_me_prnet_pw_forward = _sig("me_prnet_pw_forward", [_P, _PT, _PT, _I32, _I32, _P, _P, _I32, _I32, _PT, _P, _PT, _P])
+_me_prnet_pw_backward = _sig("me_prnet_pw_backward", [_P, _PT, _PT, _PT, _I32, _I32, _P, _I32, _I32, _I32, _P, _P, _P,
+                                                      _P, _P])
+_me_prnet_loss = _sig("me_prnet_loss", [_P, _P, _P, _P, _I32, _I32, _I32, _I32, _F, _P, _P, _P])
 _me_status_string = _sig("me_status_string", [_I32], ctypes.c_char_p)
 _me_last_error = _sig("me_last_error", [], ctypes.c_char_p)
 
@@ -97,7 +125,11 @@ EXPORTS = ["me_default_params", "me_ctx_create", "me_ctx_destroy", "me_estimate"
            "me_cnn_set_params", "me_cnn_get_params", "me_cnn_pool", "me_cnn_forward", "me_cnn_train_step",
            "me_cnn_state_bytes", "me_cnn_save_state", "me_cnn_load_state", "me_cnn_layer_forward",
            "me_cnn_layer_backward", "me_cnn_loss", "me_cnn_adamw", "me_autotune", "me_pyramid",
-           "me_default_pyramid", "me_compose_vectors"]
+           "me_default_pyramid", "me_compose_vectors", "me_prnet_num_params", "me_prnet_create", "me_prnet_destroy",
+           "me_prnet_set_params", "me_prnet_get_params", "me_prnet_forward", "me_prnet_train_step",
+           "me_prnet_dw_forward", "me_prnet_dw_backward", "me_prnet_pw_forward", "me_prnet_pw_backward",
+           "me_prnet_loss"]
+ME_NHWC, ME_NCHW = 0, 1
 ME_CNN_NPARAMS = 21699
 
 
@@ -403,3 +435,140 @@ def cnn_loss(ctx, out, mv, radius, refine_radius, dz, loss, weight=None, stream=
 
 def cnn_adamw(ctx, grads, lr, stream=None):
     _check(_me_cnn_adamw(ctx.handle, grads.data_ptr(), lr, _stream_handle(stream)))
+
+
+# ------------------------------------------------- perception residual network --
+
+def prnet_cfg(c_feat=256, c_enc=32, c_hid=64, expand=4, n_blocks=2) -> MePrnetCfg:
+    return MePrnetCfg(c_feat, c_enc, c_hid, expand, n_blocks)
+
+
+def prnet_num_params(cfg: MePrnetCfg) -> int:
+    n = _me_prnet_num_params(ctypes.byref(cfg))
+    if n < 0:
+        raise MeError(ME_E_INVAL, "invalid network configuration")
+    return n
+
+
+def feature_grid(frame_h, frame_w):
+    """Feature grid of the network for a Bayer frame: ceil(Hp/4) x ceil(Wp/4)."""
+    hp, wp = frame_h // 2, frame_w // 2
+    return (((hp - 1) // 2) // 2 + 1, ((wp - 1) // 2) // 2 + 1)
+
+
+class Prnet:
+    """A network object of the library (me_prnet_*)."""
+
+    def __init__(self, ctx: Context, cfg: MePrnetCfg | None = None):
+        self.cfg = cfg or prnet_cfg()
+        self.n_params = prnet_num_params(self.cfg)
+        h = _P()
+        _check(_me_prnet_create(ctx.handle, ctypes.byref(self.cfg), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            _check(_me_prnet_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        import numpy as np
+
+        a = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        _check(_me_prnet_set_params(self.handle, a.ctypes.data, a.size))
+
+    def get_params(self):
+        import numpy as np
+
+        a = np.empty(self.n_params, np.float32)
+        _check(_me_prnet_get_params(self.handle, a.ctypes.data, a.size))
+        return a
+
+    def forward(self, cur: torch.Tensor, z_pred: torch.Tensor, out=None, stream=None):
+        """cur: [n, H, W] (or [H, W]) uint16 mosaics; z_pred [n, c_feat, Hf, Wf] float32 or bfloat16."""
+        c = cur if cur.dim() == 3 else cur[None]
+        z = z_pred if z_pred.dim() == 4 else z_pred[None]
+        if out is None:
+            out = torch.empty_like(z)
+        dt = ME_BF16 if z.dtype == torch.bfloat16 else ME_F32
+        fr = frame_of(c[0])
+        _check(_me_prnet_forward(self.handle, ctypes.byref(fr), c.shape[0], c.stride(0), z.data_ptr(), out.data_ptr(),
+                                 dt, _stream_handle(stream)))
+        return out if z_pred.dim() == 4 else out[0]
+
+    def train_step(self, cur, z_pred, z_target, tau=-1.0, lr=1e-3, update=True, grads=None, loss=None, stream=None):
+        c = cur if cur.dim() == 3 else cur[None]
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=c.device)
+        fr = frame_of(c[0])
+        _check(_me_prnet_train_step(self.handle, ctypes.byref(fr), c.shape[0], c.stride(0), z_pred.data_ptr(),
+                                    z_target.data_ptr(), tau, lr, 1 if update else 0, _p(grads), loss.data_ptr(),
+                                    _stream_handle(stream)))
+        return loss
+
+
+def _tensor(t, layout=ME_NHWC):
+    if t is None:
+        return None
+    dt = {torch.float32: ME_F32, torch.bfloat16: ME_BF16}[t.dtype]
+    ch = t.shape[-1] if layout == ME_NHWC else t.shape[1]
+    return MeTensor(t.data_ptr(), ch, layout, dt)
+
+
+def _tp(m):
+    return ctypes.byref(m) if m is not None else None
+
+
+def prnet_dw_forward(ctx, x, w, b, stride, relu6=True, y=None, stream=None):
+    """x bfloat16 [n, H, W, C]; w float32 [C, 9]; b [C]."""
+    n, H, W, C = x.shape
+    if y is None:
+        y = torch.empty((n, (H - 1) // stride + 1, (W - 1) // stride + 1, C), dtype=torch.bfloat16, device=x.device)
+    _check(_me_prnet_dw_forward(ctx.handle, x.data_ptr(), w.data_ptr(), b.data_ptr(), n, H, W, C, stride,
+                                1 if relu6 else 0, y.data_ptr(), _stream_handle(stream)))
+    return y
+
+
+def prnet_dw_backward(ctx, x, w, dy, stride, mask=None, dx=None, grads=None, stream=None):
+    n, H, W, C = x.shape
+    _check(_me_prnet_dw_backward(ctx.handle, x.data_ptr(), w.data_ptr(), dy.data_ptr(), _p(mask), n, H, W, C, stride,
+                                 _p(dx), _p(grads), _stream_handle(stream)))
+
+
+def prnet_pw_forward(ctx, x, w, b, out, x2=None, relu6=False, add=None, mask=None, hw=None, x_layout=ME_NHWC,
+                     add_layout=ME_NHWC, out_layout=ME_NHWC, stream=None):
+    """1x1 convolution over n images of hw pixels; tensors in the given layouts
+    ([n, hw, C] or [n, C, hw] views); x2 is channels-last bfloat16."""
+    n = x.shape[0]
+    hw = hw if hw is not None else (x.shape[1] if x_layout == ME_NHWC else x.shape[2])
+    tx, tx2, ta, to = _tensor(x, x_layout), _tensor(x2), _tensor(add, add_layout), _tensor(out, out_layout)
+    _check(_me_prnet_pw_forward(ctx.handle, ctypes.byref(tx), _tp(tx2), n, hw, w.data_ptr(), _p(b), w.shape[0],
+                                1 if relu6 else 0, _tp(ta), _p(mask), ctypes.byref(to), _stream_handle(stream)))
+    return out
+
+
+def prnet_pw_backward(ctx, x, w, dy, x2=None, dx=None, dx_c0=0, dx_count=None, add=None, mask=None, grads=None,
+                      hw=None, x_layout=ME_NHWC, dy_layout=ME_NHWC, stream=None):
+    n = x.shape[0]
+    hw = hw if hw is not None else (x.shape[1] if x_layout == ME_NHWC else x.shape[2])
+    cin = w.shape[1]
+    dx_count = cin - dx_c0 if dx_count is None else dx_count
+    tx, tx2, td = _tensor(x, x_layout), _tensor(x2), _tensor(dy, dy_layout)
+    _check(_me_prnet_pw_backward(ctx.handle, ctypes.byref(tx), _tp(tx2), ctypes.byref(td), n, hw, w.data_ptr(),
+                                 w.shape[0], dx_c0, dx_count, _p(add), _p(mask), _p(dx), _p(grads),
+                                 _stream_handle(stream)))
+
+
+def prnet_loss(ctx, r, z_pred, z_target, tau=-1.0, dr=None, loss=None, stream=None):
+    n, C, Hf, Wf = r.shape
+    dr = torch.empty(r.shape, dtype=torch.bfloat16, device=r.device) if dr is None else dr
+    loss = torch.empty(1, dtype=torch.float32, device=r.device) if loss is None else loss
+    _check(_me_prnet_loss(ctx.handle, r.data_ptr(), z_pred.data_ptr(), z_target.data_ptr(), n, C, Hf, Wf, tau,
+                          dr.data_ptr(), loss.data_ptr(), _stream_handle(stream)))
+    return dr, loss

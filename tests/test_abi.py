@@ -188,3 +188,29 @@ def test_refine_validation(me):
     assert args(ctypes.c_void_p(FAKE), 0) == 1         # null network output
     p.refine_radius = 9
     assert args(ctypes.c_void_p(FAKE), FAKE) == 1
+
+
+def test_prnet_num_params_and_validation(me):
+    from oracle import prnet as P
+
+    for cfg in [(256, 32, 64, 4, 2), (16, 16, 16, 2, 0), (48, 16, 32, 3, 5)]:
+        c = me.MePrnetCfg(*cfg)
+        assert me.prnet_num_params(c) == P.n_params(P.Cfg(*cfg)), cfg
+    for bad in [(250, 32, 64, 4, 2), (256, 0, 64, 4, 2), (256, 32, 64, 0, 2), (256, 32, 64, 4, -1),
+                (1024, 32, 64, 4, 2), (256, 32, 512, 4, 1)]:
+        assert me._me_prnet_num_params(ctypes.byref(me.MePrnetCfg(*bad))) == -1, bad
+    h = ctypes.c_void_p()
+    assert me._me_prnet_create(None, ctypes.byref(me.prnet_cfg()), ctypes.byref(h)) == me.ME_E_INVAL
+    fr = _frame(me)
+    assert me._me_prnet_forward(None, ctypes.byref(fr), 1, 0, FAKE, FAKE, 0, None) == me.ME_E_INVAL
+    assert me._me_prnet_train_step(None, ctypes.byref(fr), 1, 0, FAKE, FAKE, 0.0, 0.0, 0, None, FAKE,
+                                   None) == me.ME_E_INVAL
+    assert me._me_prnet_dw_forward(None, FAKE, FAKE, FAKE, 1, 8, 8, 4, 1, 1, FAKE, None) == me.ME_E_INVAL
+    assert me._me_prnet_dw_backward(None, FAKE, FAKE, FAKE, None, 1, 8, 8, 4, 1, FAKE, FAKE, None) == me.ME_E_INVAL
+    t = me.MeTensor(FAKE, 16, 0, 1)
+    assert me._me_prnet_pw_forward(None, ctypes.byref(t), None, 1, 64, FAKE, None, 16, 0, None, None,
+                                   ctypes.byref(t), None) == me.ME_E_INVAL
+    assert me._me_prnet_pw_backward(None, ctypes.byref(t), None, ctypes.byref(t), 1, 64, FAKE, 16, 0, 16, None, None,
+                                    FAKE, FAKE, None) == me.ME_E_INVAL
+    assert me._me_prnet_loss(None, FAKE, FAKE, FAKE, 1, 16, 4, 4, 0.0, FAKE, FAKE, None) == me.ME_E_INVAL
+    assert me.feature_grid(1080, 1920) == (135, 240) and me.feature_grid(22, 10) == (3, 2)
