@@ -229,6 +229,75 @@ def gop_leg(me, ctx, frames, B, R, args):
     return out
 
 
+def prnet_bytes(cfg, Hb, Wb, n=1, zbytes=4):
+    """Algorithmic HBM bytes of one forward pass of the residual network: every
+    layer reads its inputs and writes its output once (activations bfloat16,
+    features zbytes per element), weights once."""
+    Hp, Wp = Hb // 2, Wb // 2
+    H1, W1 = (Hp + 1) // 2, (Wp + 1) // 2
+    Hf, Wf = (H1 + 1) // 2, (W1 + 1) // 2
+    P0, P1, P2 = n * Hp * Wp, n * H1 * W1, n * Hf * Wf
+    e, h, x, cz = cfg.c_enc, cfg.c_hid, cfg.c_hid * cfg.expand, cfg.c_feat
+    act = [(2 * P0 * 4 * 2)]                                  # mosaic in, planes out
+    act += [P0 * 4 * 2 + P1 * 4 * 2, P1 * 4 * 2 + P1 * e * 2, P1 * e * 2 + P2 * e * 2, P2 * e * 4]
+    act += [P2 * cz * zbytes + P2 * e * 2 + P2 * h * 2]       # projection
+    act += [cfg.n_blocks * (P2 * h * 2 + P2 * x * 2 + 2 * P2 * x * 2 + P2 * x * 2 + 2 * P2 * h * 2 + P2 * h * 2)]
+    act += [P2 * h * 2 + 2 * P2 * cz * zbytes]                # head: reads h and z_pred, writes z_out
+    params = 4 * 9 + 4 + 4 * e + e + e * 9 + e + e * e + e + (cz + e) * h + h + \
+        cfg.n_blocks * (h * x + x + 9 * x + x + x * h + h) + h * cz + cz
+    return sum(act) + 4 * params
+
+
+def prnet_leg(me, ctx, frames, z, mvs, B, H, W, args):
+    """The residual network that corrects propagated features (paper Sec. 3.3),
+    default widths (c_feat 256, c_enc 32, c_hid 64, expand 4, 2 blocks), seeded
+    parameters: forward on the warped 1080p features of one frame (time per
+    frame, algorithmic HBM bytes / time against 8 TB/s), and a training step on
+    a batch of 4 frames."""
+    import torch
+
+    cfg = me.prnet_cfg()
+    net = me.Prnet(ctx, cfg)
+    try:
+        net.set_params(me.prnet_init_params(cfg, seed=0, head_scale=0.1))
+        z = z.float()
+        zp = me.warp_features(z, mvs[0], B, H, W, ctx=ctx)
+        cur = frames[1]
+        out = torch.empty_like(zp)
+        reps = max(4, args.steps * 4)
+        for _ in range(max(1, args.warmup)):
+            net.forward(cur, zp, out=out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            net.forward(cur, zp, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        nbytes = prnet_bytes(cfg, H, W)
+        nb = 4
+        curb = torch.stack(frames[1:1 + nb])
+        zpb = torch.stack([me.warp_features(z, mvs[k], B, H, W, ctx=ctx) for k in range(nb)])
+        ztb = torch.stack([me.warp_features(z, mvs[k + 1], B, H, W, ctx=ctx) for k in range(nb)])
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        for _ in range(max(1, args.warmup)):
+            net.train_step(curb, zpb, ztb, tau=0.1, lr=1e-4, loss=loss)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        treps = max(2, args.steps)
+        for _ in range(treps):
+            net.train_step(curb, zpb, ztb, tau=0.1, lr=1e-4, loss=loss)
+        torch.cuda.synchronize()
+        train_ms = (time.perf_counter() - t0) * 1e3 / treps
+    finally:
+        net.close()
+    return {"workload": "PRNet forward on [256, 135, 240] float32 features + 1080p frame; training batch 4",
+            "params": net.n_params, "forward_ms": round(ms, 4), "frames_per_s": round(1e3 / ms, 1),
+            "algorithmic_bytes": nbytes, "achieved_gbs": round(nbytes / ms / 1e6, 1),
+            "hbm_frac": round(nbytes / ms / 1e6 / 8000.0, 4), "train_step_ms_batch4": round(train_ms, 3)}
+
+
 def batched_leg(me, ctx, args):
     """24 independent streams of 8 frames (640x480 to 3840x2160, (B, R) in
     {8, 16} x {16, 32}): 168 pairs as one graph-captured persistent launch
@@ -349,6 +418,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 24-stream batched measurement")
     ap.add_argument("--no-pyramid", action="store_true", help="skip the pyramid-search measurement")
     ap.add_argument("--no-gop", action="store_true", help="skip the group-of-pictures propagation measurement")
+    ap.add_argument("--no-prnet", action="store_true", help="skip the residual-network measurement")
     ap.add_argument("--uhd-frames", type=int, default=16, help="frames of the 4K sequence (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes (reference for HBM byte counters)")
@@ -455,6 +525,8 @@ def main():
         res["pyramid"] = pyramid_leg(me, ctx, frames, mvs, z, outs, B, R, H, W, args)
     if not args.no_gop:
         res["gop_propagation"] = gop_leg(me, ctx, frames, B, R, args)
+    if not args.no_prnet:
+        res["prnet"] = prnet_leg(me, ctx, frames, z, mvs, B, H, W, args)
     if not args.no_batched:
         res["batched_streams"] = batched_leg(me, ctx, args)
     if args.uhd_frames > 1:

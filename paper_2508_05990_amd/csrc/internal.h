@@ -165,10 +165,28 @@ hipError_t launch_dw_fwd(const uint16_t* x, const float* w, const float* b, uint
                          int S, int relu6, hipStream_t st);
 hipError_t launch_dw_dgrad(const uint16_t* dy, const float* w, const uint16_t* mask, uint16_t* dx, int n, int H, int W,
                            int C, int S, hipStream_t st);
-hipError_t launch_dw_wgrad(const uint16_t* x, const uint16_t* dy, float* partial, int nwg, int chunk, float* gw,
-                           float* gb, int n, int H, int W, int C, int S, hipStream_t st);
+int dw_wgrad_nwg(int n, int Ho, int Wo);   // workgroups (partial rows) of a depthwise weight gradient
+hipError_t launch_dw_wgrad(const uint16_t* x, const uint16_t* dy, float* partial, float* gw, float* gb, int n, int H,
+                           int W, int C, int S, hipStream_t st);
 hipError_t launch_planes(const uint16_t* m, int64_t pitch, int64_t img_stride, int n, int Hp, int Wp, uint16_t* out,
                          hipStream_t st);
+// One inverted residual block fused (inference): h_out = h + Wc ReLU6(dw(ReLU6(We h + be)) + bd) + bc,
+// activations bfloat16 channels-last [n][Hf][Wf][ch]; we / wc: packed A operands of the expansion
+// (m = x, k = ch) and compression (m = ch, k = x); wd float32 [x][9].
+struct IrArgs {
+    const uint16_t* h_in;
+    uint16_t* h_out;
+    const uint16_t* we;
+    const float* be;
+    const float* wd;
+    const float* bd;
+    const uint16_t* wc;
+    const float* bc;
+    int32_t n, Hf, Wf, ch, x;
+};
+bool ir_fused_ok(int ch, int x);
+hipError_t launch_ir_block(const IrArgs& a, hipStream_t st);
+hipError_t launch_to_nhwc(const void* src, int f32, int n, int C, int HW, uint16_t* dst, hipStream_t st);
 int prloss_blocks(int P);
 hipError_t launch_prloss(const float* r, const float* zp, const float* zt, int n, int C, int HW, float tau,
                          int32_t* nbad, uint32_t* maxbits, uint16_t* dr, float* partial, float* loss, hipStream_t st);

@@ -147,68 +147,81 @@ __device__ void stage_cols(const PwTensor& t, int koff, int p0, int p1, int HW, 
 
 // ------------------------------------------------------------ 1x1 GEMM --
 
+// One workgroup per 64-pixel tile (grid-stride over tiles); each wave computes
+// 16 pixels for every output channel.  WLDS: the packed weights are copied to
+// LDS once per workgroup and shared by its four waves and all its tiles;
+// otherwise each wave reads them from memory (caches) as it goes.
+template <bool WLDS>
 __global__ __launch_bounds__(256) void pw_kernel(PwArgs a)
 {
-    extern __shared__ uint16_t lds[];
+    extern __shared__ __align__(16) uint16_t lds[];
     const int K = a.KS * 16, ldk = K + 8;
-    const int p0 = blockIdx.x * kPx;
-    stage_rows(a.x, 0, p0, a.P, a.HW, lds, ldk);
-    int kc = a.x.C;
-    if (a.x2.p) {
-        stage_rows(a.x2, kc, p0, a.P, a.HW, lds, ldk);
-        kc += a.x2.C;
-    }
-    for (int e = threadIdx.x; e < kPx * (K - kc); e += blockDim.x) {
-        const int px = e / (K - kc), k = kc + e - px * (K - kc);
-        lds[px * ldk + k] = 0;
-    }
-    __syncthreads();
-
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, n = lane & 15;
-    const uint16_t* brow = lds + (16 * w + n) * ldk + 4 * g;
-    const uint2* wp = reinterpret_cast<const uint2*>(a.w);
     const int MT = (a.M + 15) >> 4;
-    const int p = p0 + 16 * w + n;
-    for (int mt0 = 0; mt0 < MT; mt0 += kNG) {
-        v4f32 acc[kNG];
-#pragma unroll
-        for (int t = 0; t < kNG; ++t) acc[t] = (v4f32){0.f, 0.f, 0.f, 0.f};
-        for (int ks = 0; ks < a.KS; ++ks) {
-            const v4i16 b = as_v4(*reinterpret_cast<const uint2*>(brow + ks * 16));
-#pragma unroll
-            for (int t = 0; t < kNG; ++t)
-                if (mt0 + t < MT) acc[t] = mfma(as_v4(wp[((size_t)(mt0 + t) * a.KS + ks) * 64 + lane]), b, acc[t]);
+    const size_t wwords = WLDS ? (size_t)MT * a.KS * 256 : 0;   // bfloat16 elements of the packed weights
+    uint16_t* xl = lds + wwords;
+    const uint2* wp = WLDS ? reinterpret_cast<const uint2*>(lds) : reinterpret_cast<const uint2*>(a.w);
+    if (WLDS) {
+        const uint4* src = reinterpret_cast<const uint4*>(a.w);
+        uint4* dst = reinterpret_cast<uint4*>(lds);
+        for (int e = threadIdx.x; e < (int)(wwords >> 3); e += blockDim.x) dst[e] = src[e];
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, n = lane & 15;
+    const int ntiles = (a.P + kPx - 1) / kPx;
+    int kc = a.x.C + (a.x2.p ? a.x2.C : 0);
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int p0 = tile * kPx;
+        __syncthreads();                                   // the previous tile's reads of xl are done
+        stage_rows(a.x, 0, p0, a.P, a.HW, xl, ldk);
+        if (a.x2.p) stage_rows(a.x2, a.x.C, p0, a.P, a.HW, xl, ldk);
+        for (int e = threadIdx.x; e < kPx * (K - kc); e += blockDim.x) {
+            const int px = e / (K - kc), k = kc + e - px * (K - kc);
+            xl[px * ldk + k] = 0;
         }
-        if (p < a.P) {
+        __syncthreads();
+
+        const uint16_t* brow = xl + (16 * w + n) * ldk + 4 * g;
+        const int p = p0 + 16 * w + n;
+        for (int mt0 = 0; mt0 < MT; mt0 += kNG) {
+            v4f32 acc[kNG];
 #pragma unroll
-            for (int t = 0; t < kNG; ++t) {
-                if (mt0 + t >= MT) break;
-                const int o = (mt0 + t) * 16 + 4 * g;
-                if (o >= a.M) break;
-                float v[4] = {acc[t][0], acc[t][1], acc[t][2], acc[t][3]};
-                if (a.bias) {
+            for (int t = 0; t < kNG; ++t) acc[t] = (v4f32){0.f, 0.f, 0.f, 0.f};
+            for (int ks = 0; ks < a.KS; ++ks) {
+                const v4i16 b = as_v4(*reinterpret_cast<const uint2*>(brow + ks * 16));
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) v[i] += a.bias[o + i];
-                }
-                if (a.relu6) {
+                for (int t = 0; t < kNG; ++t)
+                    if (mt0 + t < MT) acc[t] = mfma(as_v4(wp[((size_t)(mt0 + t) * a.KS + ks) * 64 + lane]), b, acc[t]);
+            }
+            if (p < a.P) {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) v[i] = relu6f(v[i]);
+                for (int t = 0; t < kNG; ++t) {
+                    if (mt0 + t >= MT) break;
+                    const int o = (mt0 + t) * 16 + 4 * g;
+                    if (o >= a.M) break;
+                    float v[4] = {acc[t][0], acc[t][1], acc[t][2], acc[t][3]};
+                    if (a.bias) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) v[i] += a.bias[o + i];
+                    }
+                    if (a.relu6) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) v[i] = relu6f(v[i]);
+                    }
+                    if (a.add.p) {
+                        const float4 d = load4(a.add, p, o, a.HW);
+                        v[0] += d.x;
+                        v[1] += d.y;
+                        v[2] += d.z;
+                        v[3] += d.w;
+                    }
+                    if (a.mask) {
+                        const float4 m = unpack4(*reinterpret_cast<const uint2*>(a.mask + (size_t)p * a.M + o));
+                        v[0] *= keep(m.x);
+                        v[1] *= keep(m.y);
+                        v[2] *= keep(m.z);
+                        v[3] *= keep(m.w);
+                    }
+                    store4(a.out, a.out_chw, a.out_f32, a.M, a.HW, p, o, make_float4(v[0], v[1], v[2], v[3]));
                 }
-                if (a.add.p) {
-                    const float4 d = load4(a.add, p, o, a.HW);
-                    v[0] += d.x;
-                    v[1] += d.y;
-                    v[2] += d.z;
-                    v[3] += d.w;
-                }
-                if (a.mask) {
-                    const float4 m = unpack4(*reinterpret_cast<const uint2*>(a.mask + (size_t)p * a.M + o));
-                    v[0] *= keep(m.x);
-                    v[1] *= keep(m.y);
-                    v[2] *= keep(m.z);
-                    v[3] *= keep(m.w);
-                }
-                store4(a.out, a.out_chw, a.out_f32, a.M, a.HW, p, o, make_float4(v[0], v[1], v[2], v[3]));
             }
         }
     }
@@ -238,7 +251,7 @@ __global__ void pw_pack_kernel(const float* __restrict__ w, int ld, int m0, int 
 // for the (mt, nt) tiles of its group; tile (mt, nt) = dW[o = mt*16..][c = nt*16..].
 __global__ __launch_bounds__(256) void pw_wgrad_kernel(PwGradArgs a)
 {
-    extern __shared__ uint16_t lds[];
+    extern __shared__ __align__(16) uint16_t lds[];
     const int MP = (a.cout + 15) & ~15, NP = (a.cin + 15) & ~15;
     uint16_t* dyT = lds;
     uint16_t* xT = lds + MP * kLdp;
@@ -307,71 +320,108 @@ __global__ __launch_bounds__(256) void pw_wgrad_kernel(PwGradArgs a)
     }
 }
 
-// grads[off_w + o*cin + c] and grads[off_b + o]: sums of the partials in workgroup order.
-__global__ void pw_wgrad_reduce_kernel(const float* __restrict__ partial, int nwg, int cin, int cout,
-                                       float* __restrict__ gw, float* __restrict__ gb)
-{
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nw = cout * cin;
-    if (e < nw) {
-        float s = 0.f;
-        for (int x = 0; x < nwg; ++x) s += partial[(size_t)x * nw + e];
-        gw[e] = s;
-    } else if (e < nw + cout) {
-        const int o = e - nw;
-        float s = 0.f;
-        for (int x = 0; x < nwg; ++x) s += partial[(size_t)nwg * nw + (size_t)x * cout + o];
-        gb[o] = s;
-    }
-}
-
 // ------------------------------------------------------------ depthwise --
 
-template <int S>
-__global__ __launch_bounds__(256) void dw_fwd_kernel(const uint16_t* __restrict__ x, const float* __restrict__ w,
-                                                     const float* __restrict__ b, uint16_t* __restrict__ y, int n, int H,
-                                                     int W, int C, int Ho, int Wo, int relu6)
+constexpr int kRun = 8;   // outputs along x per thread in the depthwise kernels
+
+__device__ __forceinline__ float4 ld4(const uint2* base, int c4n, int H, int W, int r, int c)
 {
-    const int c4n = C >> 2;
+    if (r < 0 || r >= H || c < 0 || c >= W) return make_float4(0.f, 0.f, 0.f, 0.f);
+    return unpack4(base[((size_t)r * W + c) * c4n]);
+}
+
+// Depthwise 3x3, zero padding 1, over runs of RUN outputs along x per thread:
+// a sliding 3x3 window of 4-channel vectors (3 loads per output at stride 1,
+// 6 at stride 2, instead of 9).  GRAD = false: y = b + sum_tap w[tap] x[S oy +
+// ky - 1][S ox + kx - 1], then ReLU6 if relu6.  GRAD = true (stride 1 only):
+// the input gradient dx[y][x] = sum_tap w[tap] dy[y + 1 - ky][x + 1 - kx], i.e.
+// the same pass over dy with the kernel rotated by 180 degrees, times the
+// ReLU6 derivative of mask when mask is given.
+template <int S, bool GRAD, int RUN>
+__global__ __launch_bounds__(256) void dw_fwd_kernel(const uint16_t* __restrict__ x, const float* __restrict__ w,
+                                                     const float* __restrict__ b, const uint16_t* __restrict__ mask,
+                                                     uint16_t* __restrict__ y, int n, int H, int W, int C, int Ho,
+                                                     int Wo, int relu6)
+{
+    const int c4n = C >> 2, runs = (Wo + RUN - 1) / RUN;
     const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (size_t)n * Ho * Wo * c4n) return;
+    if (e >= (size_t)n * Ho * runs * c4n) return;
     const int c4 = (int)(e % c4n);
     size_t q = e / c4n;
-    const int ox = (int)(q % Wo);
-    q /= Wo;
+    const int run = (int)(q % runs);
+    q /= runs;
     const int oy = (int)(q % Ho), img = (int)(q / Ho);
     const int c = 4 * c4;
-    float acc[4] = {b[c], b[c + 1], b[c + 2], b[c + 3]};
+    float wk[9][4];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) wk[t][i] = w[(c + i) * 9 + (GRAD ? 8 - t : t)];
+    float bias[4] = {0.f, 0.f, 0.f, 0.f};
+    if (!GRAD) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bias[i] = b[c + i];
+    }
     const uint2* xs = reinterpret_cast<const uint2*>(x) + (size_t)img * H * W * c4n + c4;
+    const int ox0 = run * RUN;
+    float4 win[3][3];
 #pragma unroll
     for (int ky = 0; ky < 3; ++ky) {
         const int iy = S * oy + ky - 1;
-        if (iy < 0 || iy >= H) continue;
+        win[ky][0] = ld4(xs, c4n, H, W, iy, S * ox0 - 1);
+        win[ky][1] = ld4(xs, c4n, H, W, iy, S * ox0);
+    }
+    uint2* ys = reinterpret_cast<uint2*>(y) + ((size_t)(img * Ho + oy) * Wo) * c4n + c4;
+    const uint2* ms = mask ? reinterpret_cast<const uint2*>(mask) + ((size_t)(img * Ho + oy) * Wo) * c4n + c4 : nullptr;
 #pragma unroll
-        for (int kx = 0; kx < 3; ++kx) {
-            const int ix = S * ox + kx - 1;
-            if (ix < 0 || ix >= W) continue;
-            const float4 v = unpack4(xs[((size_t)iy * W + ix) * c4n]);
-            const int tap = 3 * ky + kx;
-            acc[0] += w[c * 9 + tap] * v.x;
-            acc[1] += w[(c + 1) * 9 + tap] * v.y;
-            acc[2] += w[(c + 2) * 9 + tap] * v.z;
-            acc[3] += w[(c + 3) * 9 + tap] * v.w;
+    for (int j = 0; j < RUN; ++j) {
+        const int ox = ox0 + j;
+        if (ox >= Wo) break;
+        const int ixr = S * ox + 1;
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky) win[ky][2] = ld4(xs, c4n, H, W, S * oy + ky - 1, ixr);
+        float acc[4] = {bias[0], bias[1], bias[2], bias[3]};
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) {
+                const float4 v = win[ky][kx];
+                const int t = 3 * ky + kx;
+                acc[0] += wk[t][0] * v.x;
+                acc[1] += wk[t][1] * v.y;
+                acc[2] += wk[t][2] * v.z;
+                acc[3] += wk[t][3] * v.w;
+            }
+        if (!GRAD && relu6) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[i] = relu6f(acc[i]);
+        }
+        if (GRAD && ms) {
+            const float4 m = unpack4(ms[(size_t)ox * c4n]);
+            acc[0] *= keep(m.x);
+            acc[1] *= keep(m.y);
+            acc[2] *= keep(m.z);
+            acc[3] *= keep(m.w);
+        }
+        ys[(size_t)ox * c4n] = pack4(acc[0], acc[1], acc[2], acc[3]);
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky) {
+            if (S == 1) {
+                win[ky][0] = win[ky][1];
+                win[ky][1] = win[ky][2];
+            } else {
+                win[ky][0] = win[ky][2];
+                win[ky][1] = ld4(xs, c4n, H, W, S * oy + ky - 1, ixr + 1);
+            }
         }
     }
-    if (relu6) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i] = relu6f(acc[i]);
-    }
-    reinterpret_cast<uint2*>(y)[e] = pack4(acc[0], acc[1], acc[2], acc[3]);
 }
 
-// dx[n][y][x][c] = sum over taps whose output position exists of W[c][tap] dy, times the
-// ReLU6 derivative of mask (the stored input activation) when mask is given.
-template <int S>
-__global__ __launch_bounds__(256) void dw_dgrad_kernel(const uint16_t* __restrict__ dy, const float* __restrict__ w,
-                                                       const uint16_t* __restrict__ mask, uint16_t* __restrict__ dx,
-                                                       int n, int H, int W, int C, int Ho, int Wo)
+// Input gradient at stride 2: dx[n][y][x][c] = sum over the taps whose output
+// position exists of W[c][tap] dy, times the ReLU6 derivative of mask.
+__global__ __launch_bounds__(256) void dw_dgrad2_kernel(const uint16_t* __restrict__ dy, const float* __restrict__ w,
+                                                        const uint16_t* __restrict__ mask, uint16_t* __restrict__ dx,
+                                                        int n, int H, int W, int C, int Ho, int Wo)
 {
     const int c4n = C >> 2;
     const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -387,14 +437,14 @@ __global__ __launch_bounds__(256) void dw_dgrad_kernel(const uint16_t* __restric
 #pragma unroll
     for (int ky = 0; ky < 3; ++ky) {
         const int ty = iy + 1 - ky;
-        if (ty < 0 || ty % S) continue;
-        const int oy = ty / S;
+        if (ty < 0 || (ty & 1)) continue;
+        const int oy = ty >> 1;
         if (oy >= Ho) continue;
 #pragma unroll
         for (int kx = 0; kx < 3; ++kx) {
             const int tx = ix + 1 - kx;
-            if (tx < 0 || tx % S) continue;
-            const int ox = tx / S;
+            if (tx < 0 || (tx & 1)) continue;
+            const int ox = tx >> 1;
             if (ox >= Wo) continue;
             const float4 d = unpack4(ds[((size_t)oy * Wo + ox) * c4n]);
             const int tap = 3 * ky + kx;
@@ -414,10 +464,10 @@ __global__ __launch_bounds__(256) void dw_dgrad_kernel(const uint16_t* __restric
     reinterpret_cast<uint2*>(dx)[e] = pack4(acc[0], acc[1], acc[2], acc[3]);
 }
 
-// Partial weight and bias gradients of one workgroup's output pixels:
-// partial[wg][c][tap] (tap 9 = bias).  Threads are (channel group, lane of
-// the group); each lane accumulates every tpg-th pixel, and the lanes of a
-// group are summed in lane order.
+// Partial weight and bias gradients: partial[wg][c][tap] (tap 9 = bias) over
+// the workgroup's units (image, output row, run of kRun outputs).  Threads are
+// (channel group, lane of the group); each lane takes every tpg-th unit with a
+// sliding input window, and the lanes of a group are summed in lane order.
 template <int S>
 __global__ __launch_bounds__(256) void dw_wgrad_kernel(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dy,
                                                        float* __restrict__ partial, int n, int H, int W, int C, int Ho,
@@ -426,38 +476,58 @@ __global__ __launch_bounds__(256) void dw_wgrad_kernel(const uint16_t* __restric
     __shared__ float red[256 * 41];
     const int G = C >> 2, tpg = blockDim.x / G;
     const int grp = threadIdx.x % G, sub = threadIdx.x / G;
-    const int P = n * Ho * Wo;
-    const int pb = blockIdx.x * chunk, pe = min(P, pb + chunk);
+    const int runs = (Wo + kRun - 1) / kRun, U = n * Ho * runs;
+    const int ub = blockIdx.x * chunk, ue = min(U, ub + chunk);
     float acc[10][4];
 #pragma unroll
     for (int t = 0; t < 10; ++t)
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc[t][i] = 0.f;
     if (sub < tpg) {
-        const uint2* xs = reinterpret_cast<const uint2*>(x) + grp;
-        const uint2* ds = reinterpret_cast<const uint2*>(dy) + grp;
-        for (int q = pb + sub; q < pe; q += tpg) {
-            const int img = q / (Ho * Wo), rem = q - img * Ho * Wo;
-            const int oy = rem / Wo, ox = rem - oy * Wo;
-            const float4 d = unpack4(ds[(size_t)q * G]);
-            acc[9][0] += d.x;
-            acc[9][1] += d.y;
-            acc[9][2] += d.z;
-            acc[9][3] += d.w;
+        for (int u = ub + sub; u < ue; u += tpg) {
+            const int run = u % runs, q = u / runs, oy = q % Ho, img = q / Ho;
+            const uint2* xs = reinterpret_cast<const uint2*>(x) + (size_t)img * H * W * G + grp;
+            const uint2* ds = reinterpret_cast<const uint2*>(dy) + ((size_t)(img * Ho + oy) * Wo) * G + grp;
+            const int ox0 = run * kRun;
+            float4 win[3][3];
 #pragma unroll
             for (int ky = 0; ky < 3; ++ky) {
                 const int iy = S * oy + ky - 1;
-                if (iy < 0 || iy >= H) continue;
+                win[ky][0] = ld4(xs, G, H, W, iy, S * ox0 - 1);
+                win[ky][1] = ld4(xs, G, H, W, iy, S * ox0);
+            }
 #pragma unroll
-                for (int kx = 0; kx < 3; ++kx) {
-                    const int ix = S * ox + kx - 1;
-                    if (ix < 0 || ix >= W) continue;
-                    const float4 v = unpack4(xs[(((size_t)img * H + iy) * W + ix) * G]);
-                    const int tap = 3 * ky + kx;
-                    acc[tap][0] += d.x * v.x;
-                    acc[tap][1] += d.y * v.y;
-                    acc[tap][2] += d.z * v.z;
-                    acc[tap][3] += d.w * v.w;
+            for (int j = 0; j < kRun; ++j) {
+                const int ox = ox0 + j;
+                if (ox >= Wo) break;
+                const int ixr = S * ox + 1;
+#pragma unroll
+                for (int ky = 0; ky < 3; ++ky) win[ky][2] = ld4(xs, G, H, W, S * oy + ky - 1, ixr);
+                const float4 d = unpack4(ds[(size_t)ox * G]);
+                acc[9][0] += d.x;
+                acc[9][1] += d.y;
+                acc[9][2] += d.z;
+                acc[9][3] += d.w;
+#pragma unroll
+                for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+                    for (int kx = 0; kx < 3; ++kx) {
+                        const float4 v = win[ky][kx];
+                        const int t = 3 * ky + kx;
+                        acc[t][0] += d.x * v.x;
+                        acc[t][1] += d.y * v.y;
+                        acc[t][2] += d.z * v.z;
+                        acc[t][3] += d.w * v.w;
+                    }
+#pragma unroll
+                for (int ky = 0; ky < 3; ++ky) {
+                    if (S == 1) {
+                        win[ky][0] = win[ky][1];
+                        win[ky][1] = win[ky][2];
+                    } else {
+                        win[ky][0] = win[ky][2];
+                        win[ky][1] = ld4(xs, G, H, W, S * oy + ky - 1, ixr + 1);
+                    }
                 }
             }
         }
@@ -477,16 +547,209 @@ __global__ __launch_bounds__(256) void dw_wgrad_kernel(const uint16_t* __restric
     }
 }
 
-__global__ void dw_wgrad_reduce_kernel(const float* __restrict__ partial, int nwg, int C, float* __restrict__ gw,
-                                       float* __restrict__ gb)
+// Sums of partial rows in a fixed order: element e (< m) of the output is
+// sum over rows x of partial[x * stride + e], taken as four interleaved
+// running sums (rows x = q mod 4, in order) added in q order.  mode 0: out[e];
+// mode 1 (depthwise layout [c][10]): tap < 9 -> gw[c*9 + tap], tap 9 -> gb[c].
+__global__ __launch_bounds__(256) void reduce_rows_kernel(const float* __restrict__ partial, int nrows, size_t stride,
+                                                          int m, int mode, float* __restrict__ gw,
+                                                          float* __restrict__ gb)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= C * 10) return;
-    const int c = e / 10, tap = e - c * 10;
+    __shared__ float red[4][64];
+    const int j = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + j;
     float s = 0.f;
-    for (int x = 0; x < nwg; ++x) s += partial[((size_t)x * C + c) * 10 + tap];
-    if (tap < 9) gw[c * 9 + tap] = s;
-    else gb[c] = s;
+    if (e < m)
+        for (int x = q; x < nrows; x += 4) s += partial[(size_t)x * stride + e];
+    red[q][j] = s;
+    __syncthreads();
+    if (q != 0 || e >= m) return;
+    const float t = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
+    if (mode == 0) {
+        gw[e] = t;
+    } else {
+        const int c = e / 10, tap = e - c * 10;
+        if (tap < 9) gw[c * 9 + tap] = t;
+        else gb[c] = t;
+    }
+}
+
+// ------------------------------------------------- fused residual block --
+
+// One inverted residual block in one pass (inference): h_out = h + Wc v + bc,
+// v = ReLU6(dw3x3(u) + bd), u = ReLU6(We h + be), with u and v kept in LDS.
+// A workgroup owns an 8 x 8 tile of output pixels.  It stages h over the
+// tile and its one-pixel halo (10 x 10 = 100 pixels, padded to 7 MFMA column
+// tiles), then walks the expanded channels in chunks of 64: expand the chunk
+// for all halo pixels (u = 0 outside the image: the depthwise zero padding),
+// depthwise-filter it into v (64 x 64), and fold v into the compression
+// accumulators, which stay in registers across chunks.  Rounding points match
+// the layer-by-layer path (u, v and h_out are bfloat16).  About 44 KB of LDS
+// per workgroup at 64 hidden channels, so three workgroups share a CU.
+constexpr int kIrT = 8, kIrHW = kIrT + 2, kIrHalo = kIrHW * kIrHW, kIrRows = 112;
+constexpr int kIrChunk = 64, kIrLd = kIrChunk + 8;
+
+template <int CH>
+__global__ __launch_bounds__(256) void ir_block_kernel(IrArgs a)
+{
+    extern __shared__ __align__(16) uint16_t lds[];
+    const int X = a.x;
+    constexpr int ldh = CH + 8;
+    uint16_t* hl = lds;                                   // [112][CH + 8]   h over tile + halo
+    uint16_t* ul = hl + kIrRows * ldh;                     // [112][72]       u, one chunk
+    uint16_t* vl = ul + kIrRows * kIrLd;                   // [64][72]        v, one chunk
+    float* wl = reinterpret_cast<float*>(vl + kIrT * kIrT * kIrLd);   // [64][9] depthwise weights, then [64] bias
+    const int tiles_x = (a.Wf + kIrT - 1) / kIrT, tiles_y = (a.Hf + kIrT - 1) / kIrT;
+    const int img = blockIdx.x / (tiles_x * tiles_y), tr = blockIdx.x - img * tiles_x * tiles_y;
+    const int y0 = (tr / tiles_x) * kIrT, x0 = (tr % tiles_x) * kIrT;
+    constexpr int c4n = CH >> 2;
+    const uint2* hin = reinterpret_cast<const uint2*>(a.h_in) + (size_t)img * a.Hf * a.Wf * c4n;
+
+    for (int e = threadIdx.x; e < kIrRows * c4n; e += blockDim.x) {
+        const int hp = e / c4n, c4 = e - hp * c4n;
+        uint2 v = make_uint2(0u, 0u);
+        if (hp < kIrHalo) {
+            const int gy = y0 + hp / kIrHW - 1, gx = x0 + hp % kIrHW - 1;
+            if (gy >= 0 && gy < a.Hf && gx >= 0 && gx < a.Wf) v = hin[((size_t)gy * a.Wf + gx) * c4n + c4];
+        }
+        *reinterpret_cast<uint2*>(hl + hp * ldh + 4 * c4) = v;
+    }
+
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, n = lane & 15;
+    const uint2* we = reinterpret_cast<const uint2*>(a.we);
+    const uint2* wc = reinterpret_cast<const uint2*>(a.wc);
+    constexpr int KSe = CH >> 4, MTc = CH >> 4;
+    const int KSc = X >> 4;
+    // expansion column tiles of this wave: w and w + 4 (tile 7 does not exist)
+    bool inside[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int hp = (w + 4 * j) * 16 + n;
+        const int gy = y0 + hp / kIrHW - 1, gx = x0 + hp % kIrHW - 1;
+        inside[j] = hp < kIrHalo && gy >= 0 && gy < a.Hf && gx >= 0 && gx < a.Wf;
+    }
+    v4f32 acc2[MTc];
+#pragma unroll
+    for (int t = 0; t < MTc; ++t) acc2[t] = (v4f32){0.f, 0.f, 0.f, 0.f};
+    const int c4 = threadIdx.x & 15;                       // channel group of this thread in the depthwise step
+
+#pragma unroll 1
+    for (int q = 0; q < X / kIrChunk; ++q) {
+        __syncthreads();                                   // h staged / previous chunk's u, v and weights read
+        for (int e = threadIdx.x; e < kIrChunk * 10; e += blockDim.x) {
+            const int cc = e / 10, t = e - cc * 10;
+            wl[e] = t < 9 ? a.wd[(q * kIrChunk + cc) * 9 + t] : a.bd[q * kIrChunk + cc];
+        }
+        // expand channels [64 q, 64 q + 64) of the halo pixels
+#pragma unroll 1
+        for (int j = 0; j < 2; ++j) {
+            const int nt = w + 4 * j;
+            if (nt * 16 >= kIrRows) break;
+            const int hp = nt * 16 + n;
+            const uint16_t* brow = hl + hp * ldh + 4 * g;
+            v4f32 acc[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[t] = (v4f32){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < KSe; ++ks) {
+                const v4i16 b = as_v4(*reinterpret_cast<const uint2*>(brow + ks * 16));
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    acc[t] = mfma(as_v4(we[((size_t)(4 * q + t) * KSe + ks) * 64 + lane]), b, acc[t]);
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int o = 16 * t + 4 * g;                    // channel within the chunk
+                float v[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[i] = inside[j] ? relu6f(acc[t][i] + a.be[q * kIrChunk + o + i]) : 0.f;
+                *reinterpret_cast<uint2*>(ul + hp * kIrLd + o) = pack4(v[0], v[1], v[2], v[3]);
+            }
+        }
+        __syncthreads();
+        // depthwise: 64 pixels x 16 channel groups, 4 per thread
+#pragma unroll 1
+        for (int j = 0; j < 4; ++j) {
+            const int px = (threadIdx.x >> 4) + 16 * j, ty = px >> 3, tx = px & 7;
+            const float* wk = wl + 4 * c4 * 10;
+            float acc[4] = {wk[9], wk[19], wk[29], wk[39]};
+#pragma unroll
+            for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+                for (int kx = 0; kx < 3; ++kx) {
+                    const float4 u =
+                        unpack4(*reinterpret_cast<const uint2*>(ul + ((ty + ky) * kIrHW + tx + kx) * kIrLd + 4 * c4));
+                    const int t = 3 * ky + kx;
+                    acc[0] += wk[t] * u.x;
+                    acc[1] += wk[10 + t] * u.y;
+                    acc[2] += wk[20 + t] * u.z;
+                    acc[3] += wk[30 + t] * u.w;
+                }
+            *reinterpret_cast<uint2*>(vl + px * kIrLd + 4 * c4) =
+                pack4(relu6f(acc[0]), relu6f(acc[1]), relu6f(acc[2]), relu6f(acc[3]));
+        }
+        __syncthreads();
+        // compression, column tile w (pixels 16 w .. 16 w + 15)
+        const uint16_t* brow = vl + (w * 16 + n) * kIrLd + 4 * g;
+#pragma unroll
+        for (int ks = 0; ks < kIrChunk / 16; ++ks) {
+            const v4i16 b = as_v4(*reinterpret_cast<const uint2*>(brow + ks * 16));
+#pragma unroll
+            for (int t = 0; t < MTc; ++t)
+                acc2[t] = mfma(as_v4(wc[((size_t)t * KSc + 4 * q + ks) * 64 + lane]), b, acc2[t]);
+        }
+    }
+
+    // h_out = h + Wc v + bc at pixel 16 w + n of the tile
+    const int px = w * 16 + n, ty = px >> 3, tx = px & 7, gy = y0 + ty, gx = x0 + tx;
+    if (gy >= a.Hf || gx >= a.Wf) return;
+    const uint16_t* skip = hl + ((ty + 1) * kIrHW + tx + 1) * ldh;
+    uint2* hout = reinterpret_cast<uint2*>(a.h_out) + ((size_t)img * a.Hf * a.Wf + (size_t)gy * a.Wf + gx) * c4n;
+#pragma unroll
+    for (int t = 0; t < MTc; ++t) {
+        const int o = t * 16 + 4 * g;
+        const float4 sk = unpack4(*reinterpret_cast<const uint2*>(skip + o));
+        hout[o >> 2] = pack4(acc2[t][0] + a.bc[o] + sk.x, acc2[t][1] + a.bc[o + 1] + sk.y,
+                             acc2[t][2] + a.bc[o + 2] + sk.z, acc2[t][3] + a.bc[o + 3] + sk.w);
+    }
+}
+
+// -------------------------------------------------------------- layout --
+
+// [n][C][HW] (float32 or bfloat16) -> [n][HW][C] bfloat16, through a 64 x 64 LDS
+// tile: reads run along pixels, writes along channels (C a multiple of 4).
+__global__ __launch_bounds__(256) void to_nhwc_kernel(const void* __restrict__ src, int f32, int C, int HW,
+                                                      uint16_t* __restrict__ dst)
+{
+    __shared__ uint16_t t[64][66];
+    const int p0 = blockIdx.x * 64, c0 = blockIdx.y * 64, img = blockIdx.z;
+    const int col = 4 * (threadIdx.x & 15);
+#pragma unroll
+    for (int pass = 0; pass < 4; ++pass) {
+        const int r = (threadIdx.x >> 4) + 16 * pass, c = c0 + r;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int px = p0 + col + i;
+            float v = 0.f;
+            if (c < C && px < HW) {
+                const size_t idx = ((size_t)img * C + c) * HW + px;
+                v = f32 ? static_cast<const float*>(src)[idx] : bf2f(static_cast<const uint16_t*>(src)[idx]);
+            }
+            t[r][col + i] = f2bf(v);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int idx = threadIdx.x + 256 * k, px = idx >> 4, c4 = idx & 15;
+        const int c = c0 + 4 * c4;
+        if (p0 + px < HW && c < C) {
+            uint2 v;
+            v.x = (uint32_t)t[4 * c4][px] | (uint32_t)t[4 * c4 + 1][px] << 16;
+            v.y = (uint32_t)t[4 * c4 + 2][px] | (uint32_t)t[4 * c4 + 3][px] << 16;
+            *reinterpret_cast<uint2*>(dst + ((size_t)img * HW + p0 + px) * C + c) = v;
+        }
+    }
 }
 
 // ---------------------------------------------------------------- input --
@@ -529,6 +792,7 @@ __global__ __launch_bounds__(256) void prloss_stats_kernel(const float* __restri
         const int img = p / HW, hw = p - img * HW;
         const size_t base = (size_t)img * C * HW + hw;
         float s = 0.f;
+#pragma unroll 8
         for (int c = 0; c < C; ++c) {
             const size_t i = base + (size_t)c * HW;
             const float t = zt[i] - zp[i];
@@ -567,13 +831,15 @@ __global__ __launch_bounds__(256) void prloss_grad_kernel(const float* __restric
         float wpos = 1.f / (float)P;
         if (tau >= 0.f && nb > 0 && ng > 0) {
             float s = 0.f;
-            for (int c = 0; c < C; ++c) {
+    #pragma unroll 8
+        for (int c = 0; c < C; ++c) {
                 const size_t i = base + (size_t)c * HW;
                 s += fabsf(zt[i] - zp[i]);
             }
             wpos = (s / (float)C > tau) ? 0.5f / (float)nb : 0.5f / (float)ng;
         }
         const float wgt = wpos / (float)C;
+#pragma unroll 8
         for (int c = 0; c < C; ++c) {
             const size_t i = base + (size_t)c * HW;
             const float x = r[i] - (zt[i] - zp[i]);
@@ -642,13 +908,26 @@ static hipError_t allow_lds(const void* k, size_t bytes)
     return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+constexpr size_t kPwWeightsLds = 96 * 1024;   // packed weights up to this size go to LDS
+
 hipError_t launch_pw(const PwArgs& a, hipStream_t st)
 {
     if (a.P <= 0) return hipSuccess;
-    const size_t lds = pw_lds_bytes(a.KS);
-    hipError_t e = allow_lds(reinterpret_cast<const void*>(pw_kernel), lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(pw_kernel, dim3(div_up(a.P, kPx)), dim3(256), lds, st, a);
+    const size_t wbytes = (size_t)((a.M + 15) >> 4) * a.KS * 512;
+    const int ntiles = div_up(a.P, kPx);
+    if (wbytes <= kPwWeightsLds && wbytes + pw_lds_bytes(a.KS) <= 158 * 1024) {
+        const size_t lds = wbytes + pw_lds_bytes(a.KS);
+        hipError_t e = allow_lds(reinterpret_cast<const void*>(pw_kernel<true>), lds);
+        if (e != hipSuccess) return e;
+        // several tiles per workgroup amortise the weight copy once the chip is full
+        const int grid = ntiles < 1024 ? ntiles : 1024;
+        hipLaunchKernelGGL(pw_kernel<true>, dim3(grid), dim3(256), lds, st, a);
+    } else {
+        const size_t lds = pw_lds_bytes(a.KS);
+        hipError_t e = allow_lds(reinterpret_cast<const void*>(pw_kernel<false>), lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(pw_kernel<false>, dim3(ntiles), dim3(256), lds, st, a);
+    }
     return hipGetLastError();
 }
 
@@ -670,41 +949,68 @@ hipError_t launch_pw_wgrad(const PwGradArgs& a, float* gw, float* gb, hipStream_
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(pw_wgrad_kernel, dim3(nwg, pw_wgrad_groups(a.cin, a.cout)), dim3(256), lds, st, a);
     }
-    const int m = a.cout * a.cin + a.cout;
-    hipLaunchKernelGGL(pw_wgrad_reduce_kernel, dim3(div_up(m, 256)), dim3(256), 0, st, a.partial, a.P > 0 ? nwg : 0,
-                       a.cin, a.cout, gw, gb);
+    const int rows = a.P > 0 ? nwg : 0, mw = a.cout * a.cin;
+    hipLaunchKernelGGL(reduce_rows_kernel, dim3(div_up(mw, 64)), dim3(256), 0, st, a.partial, rows, (size_t)mw, mw, 0,
+                       gw, gb);
+    hipLaunchKernelGGL(reduce_rows_kernel, dim3(div_up(a.cout, 64)), dim3(256), 0, st, a.partial + (size_t)rows * mw,
+                       rows, (size_t)a.cout, a.cout, 0, gb, gb);
     return hipGetLastError();
+}
+
+// Runs of kRun outputs per thread when that still leaves enough threads to fill the chip, else one.
+template <int S, bool GRAD>
+static void dw_launch(const uint16_t* x, const float* w, const float* b, const uint16_t* mask, uint16_t* y, int n, int H,
+                      int W, int C, int Ho, int Wo, int relu6, hipStream_t st)
+{
+    const size_t m8 = (size_t)n * Ho * div_up(Wo, kRun) * (C >> 2);
+    if (m8 >= (size_t)1 << 17) {
+        hipLaunchKernelGGL((dw_fwd_kernel<S, GRAD, kRun>), dim3((unsigned)((m8 + 255) / 256)), dim3(256), 0, st, x, w,
+                           b, mask, y, n, H, W, C, Ho, Wo, relu6);
+    } else {
+        const size_t m1 = (size_t)n * Ho * Wo * (C >> 2);
+        hipLaunchKernelGGL((dw_fwd_kernel<S, GRAD, 1>), dim3((unsigned)((m1 + 255) / 256)), dim3(256), 0, st, x, w, b,
+                           mask, y, n, H, W, C, Ho, Wo, relu6);
+    }
 }
 
 hipError_t launch_dw_fwd(const uint16_t* x, const float* w, const float* b, uint16_t* y, int n, int H, int W, int C,
                          int S, int relu6, hipStream_t st)
 {
     const int Ho = (H - 1) / S + 1, Wo = (W - 1) / S + 1;
-    const size_t m = (size_t)n * Ho * Wo * (C >> 2);
-    if (m == 0) return hipSuccess;
-    const dim3 grid((unsigned)((m + 255) / 256));
-    if (S == 1) hipLaunchKernelGGL(dw_fwd_kernel<1>, grid, dim3(256), 0, st, x, w, b, y, n, H, W, C, Ho, Wo, relu6);
-    else hipLaunchKernelGGL(dw_fwd_kernel<2>, grid, dim3(256), 0, st, x, w, b, y, n, H, W, C, Ho, Wo, relu6);
+    if ((size_t)n * Ho * Wo * C == 0) return hipSuccess;
+    if (S == 1) dw_launch<1, false>(x, w, b, nullptr, y, n, H, W, C, Ho, Wo, relu6, st);
+    else dw_launch<2, false>(x, w, b, nullptr, y, n, H, W, C, Ho, Wo, relu6, st);
     return hipGetLastError();
 }
 
 hipError_t launch_dw_dgrad(const uint16_t* dy, const float* w, const uint16_t* mask, uint16_t* dx, int n, int H, int W,
                            int C, int S, hipStream_t st)
 {
-    const int Ho = (H - 1) / S + 1, Wo = (W - 1) / S + 1;
+    if ((size_t)n * H * W * C == 0) return hipSuccess;
+    if (S == 1) {
+        dw_launch<1, true>(dy, w, nullptr, mask, dx, n, H, W, C, H, W, 0, st);
+        return hipGetLastError();
+    }
+    const int Ho = (H - 1) / 2 + 1, Wo = (W - 1) / 2 + 1;
     const size_t m = (size_t)n * H * W * (C >> 2);
-    if (m == 0) return hipSuccess;
-    const dim3 grid((unsigned)((m + 255) / 256));
-    if (S == 1) hipLaunchKernelGGL(dw_dgrad_kernel<1>, grid, dim3(256), 0, st, dy, w, mask, dx, n, H, W, C, Ho, Wo);
-    else hipLaunchKernelGGL(dw_dgrad_kernel<2>, grid, dim3(256), 0, st, dy, w, mask, dx, n, H, W, C, Ho, Wo);
+    hipLaunchKernelGGL(dw_dgrad2_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, dy, w, mask, dx, n, H, W,
+                       C, Ho, Wo);
     return hipGetLastError();
 }
 
-hipError_t launch_dw_wgrad(const uint16_t* x, const uint16_t* dy, float* partial, int nwg, int chunk, float* gw,
-                           float* gb, int n, int H, int W, int C, int S, hipStream_t st)
+int dw_wgrad_nwg(int n, int Ho, int Wo)
+{
+    const int U = n * Ho * div_up(Wo, kRun);
+    return U < 256 ? U : 256;
+}
+
+hipError_t launch_dw_wgrad(const uint16_t* x, const uint16_t* dy, float* partial, float* gw, float* gb, int n, int H,
+                           int W, int C, int S, hipStream_t st)
 {
     const int Ho = (H - 1) / S + 1, Wo = (W - 1) / S + 1;
+    const int nwg = dw_wgrad_nwg(n, Ho, Wo);
     if (nwg > 0) {
+        const int chunk = div_up(n * Ho * div_up(Wo, kRun), nwg);
         if (S == 1)
             hipLaunchKernelGGL(dw_wgrad_kernel<1>, dim3(nwg), dim3(256), 0, st, x, dy, partial, n, H, W, C, Ho, Wo,
                                chunk);
@@ -712,7 +1018,8 @@ hipError_t launch_dw_wgrad(const uint16_t* x, const uint16_t* dy, float* partial
             hipLaunchKernelGGL(dw_wgrad_kernel<2>, dim3(nwg), dim3(256), 0, st, x, dy, partial, n, H, W, C, Ho, Wo,
                                chunk);
     }
-    hipLaunchKernelGGL(dw_wgrad_reduce_kernel, dim3(div_up(C * 10, 256)), dim3(256), 0, st, partial, nwg, C, gw, gb);
+    hipLaunchKernelGGL(reduce_rows_kernel, dim3(div_up(C * 10, 64)), dim3(256), 0, st, partial, nwg, (size_t)C * 10,
+                       C * 10, 1, gw, gb);
     return hipGetLastError();
 }
 
@@ -723,6 +1030,44 @@ hipError_t launch_planes(const uint16_t* m, int64_t pitch, int64_t img_stride, i
     if (e == 0) return hipSuccess;
     hipLaunchKernelGGL(planes_kernel, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, st, m, pitch, img_stride, n, Hp,
                        Wp, out);
+    return hipGetLastError();
+}
+
+size_t ir_lds_bytes(int ch, int x)
+{
+    (void)x;
+    return (size_t)(kIrRows * (ch + 8) + kIrRows * kIrLd + kIrT * kIrT * kIrLd) * sizeof(uint16_t) +
+           kIrChunk * 10 * sizeof(float);
+}
+
+bool ir_fused_ok(int ch, int x)
+{
+    return (ch == 16 || ch == 32 || ch == 48 || ch == 64 || ch == 96 || ch == 128) && x % kIrChunk == 0 &&
+           ir_lds_bytes(ch, x) <= 64 * 1024;
+}
+
+hipError_t launch_ir_block(const IrArgs& a, hipStream_t st)
+{
+    const int tiles = a.n * div_up(a.Hf, kIrT) * div_up(a.Wf, kIrT);
+    if (tiles == 0) return hipSuccess;
+    if (!ir_fused_ok(a.ch, a.x)) return hipErrorInvalidValue;
+    const size_t lds = ir_lds_bytes(a.ch, a.x);
+    switch (a.ch) {
+    case 16: hipLaunchKernelGGL(ir_block_kernel<16>, dim3(tiles), dim3(256), lds, st, a); break;
+    case 32: hipLaunchKernelGGL(ir_block_kernel<32>, dim3(tiles), dim3(256), lds, st, a); break;
+    case 48: hipLaunchKernelGGL(ir_block_kernel<48>, dim3(tiles), dim3(256), lds, st, a); break;
+    case 64: hipLaunchKernelGGL(ir_block_kernel<64>, dim3(tiles), dim3(256), lds, st, a); break;
+    case 96: hipLaunchKernelGGL(ir_block_kernel<96>, dim3(tiles), dim3(256), lds, st, a); break;
+    case 128: hipLaunchKernelGGL(ir_block_kernel<128>, dim3(tiles), dim3(256), lds, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_to_nhwc(const void* src, int f32, int n, int C, int HW, uint16_t* dst, hipStream_t st)
+{
+    if ((size_t)n * C * HW == 0) return hipSuccess;
+    hipLaunchKernelGGL(to_nhwc_kernel, dim3(div_up(HW, 64), div_up(C, 64), n), dim3(256), 0, st, src, f32, C, HW, dst);
     return hipGetLastError();
 }
 

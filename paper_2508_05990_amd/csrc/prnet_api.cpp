@@ -106,14 +106,16 @@ size_t pw_partial_floats(int P, int cin, int cout)
     return (size_t)div_up(P, wgrad_chunk(P, kWgTarget)) * ((size_t)cout * cin + cout);
 }
 
-size_t dw_partial_floats(int P, int C) { return (size_t)div_up(P, wgrad_chunk(P, kWgTarget)) * C * 10; }
+// Partial floats of a depthwise weight gradient over n images of H x W inputs.
+size_t dw_partial_floats(int n, int H, int W, int S, int C)
+{
+    return (size_t)dw_wgrad_nwg(n, osz(H, S), osz(W, S)) * C * 10;
+}
 
 hipError_t dw_wgrad(const uint16_t* x, const uint16_t* dy, float* partial, float* gw, float* gb, int n, int H, int W,
                     int C, int S, hipStream_t st)
 {
-    const int P = n * osz(H, S) * osz(W, S);
-    const int chunk = wgrad_chunk(P, kWgTarget);
-    return launch_dw_wgrad(x, dy, partial, P > 0 ? div_up(P, chunk) : 0, chunk, gw, gb, n, H, W, C, S, st);
+    return launch_dw_wgrad(x, dy, partial, gw, gb, n, H, W, C, S, st);
 }
 
 }  // namespace
@@ -138,7 +140,7 @@ struct me_prnet_s {
     size_t partial_cap = 0;
     // workspace views for the current call
     int n = 0, Hp = 0, Wp = 0, H1 = 0, W1 = 0, Hf = 0, Wf = 0;
-    uint16_t *a0, *e1, *e2, *e3, *e4;
+    uint16_t *a0, *e1, *e2, *e3, *e4, *zl;
     std::vector<uint16_t*> h, u, v_;
     float* r;
     uint16_t *dr, *gA, *gB, *dh[2];
@@ -197,6 +199,7 @@ me_status layout(me_prnet net, int n, int Hp, int Wp, bool train)
     for (int k = 0; k <= nb; ++k) sz.push_back(P2 * c.c_hid * 2);   // h
     for (int k = 0; k < nb; ++k) sz.push_back(P2 * X * 2);          // u
     for (int k = 0; k < nb; ++k) sz.push_back(P2 * X * 2);          // v
+    sz.push_back(P2 * c.c_feat * 2);                                  // z_pred, channels-last bfloat16
     size_t gmax = 0;
     if (train) {
         sz.push_back(P2 * c.c_feat * 4);         // r
@@ -231,6 +234,7 @@ me_status layout(me_prnet net, int n, int Hp, int Wp, bool train)
     for (int k = 0; k <= nb; ++k) net->h[k] = (uint16_t*)take();
     for (int k = 0; k < nb; ++k) net->u[k] = (uint16_t*)take();
     for (int k = 0; k < nb; ++k) net->v_[k] = (uint16_t*)take();
+    net->zl = (uint16_t*)take();
     if (train) {
         net->r = (float*)take();
         net->dr = (uint16_t*)take();
@@ -244,13 +248,13 @@ me_status layout(me_prnet net, int n, int Hp, int Wp, bool train)
         net->lpart = (float*)take();
         size_t pf = 0;
         // partials: the largest layer reduction
-        pf = std::max(pf, dw_partial_floats((int)P1, 4));
+        pf = std::max(pf, dw_partial_floats(n, Hp, Wp, 2, 4));
         pf = std::max(pf, pw_partial_floats((int)P1, 4, c.c_enc));
-        pf = std::max(pf, dw_partial_floats((int)P2, c.c_enc));
+        pf = std::max(pf, dw_partial_floats(n, H1, W1, 2, c.c_enc));
         pf = std::max(pf, pw_partial_floats((int)P2, c.c_enc, c.c_enc));
         pf = std::max(pf, pw_partial_floats((int)P2, c.c_feat + c.c_enc, c.c_hid));
         pf = std::max(pf, pw_partial_floats((int)P2, c.c_hid, X));
-        pf = std::max(pf, dw_partial_floats((int)P2, X));
+        pf = std::max(pf, dw_partial_floats(n, Hf, Wf, 1, X));
         pf = std::max(pf, pw_partial_floats((int)P2, X, c.c_hid));
         pf = std::max(pf, pw_partial_floats((int)P2, c.c_hid, c.c_feat));
         st = grow(&net->partial, &net->partial_cap, pf * 4);
@@ -304,10 +308,31 @@ hipError_t run_forward(me_prnet net, const me_frame* cur, int64_t frame_stride, 
                           c.c_enc, 2, 1, st);
     if (e == hipSuccess) e = launch_pw(pw_args(net, L[3], nhwc(net->e3, c.c_enc), none(), HW2, P2, net->e4), st);
     const PwTensor z{zp, c.c_feat, 1, z_bf16 ? 0 : 1};
-    if (e == hipSuccess) e = launch_pw(pw_args(net, L[4], z, nhwc(net->e4, c.c_enc), HW2, P2, net->h[0]), st);
+    if (e == hipSuccess) e = launch_to_nhwc(zp, z_bf16 ? 0 : 1, n, c.c_feat, HW2, net->zl, st);
+    if (e == hipSuccess)
+        e = launch_pw(pw_args(net, L[4], nhwc(net->zl, c.c_feat), nhwc(net->e4, c.c_enc), HW2, P2, net->h[0]), st);
     const int X = c.c_hid * c.expand;
+    const bool fused = !train && ir_fused_ok(c.c_hid, X);   // training keeps u and v for the backward pass
     for (int k = 0; k < c.n_blocks && e == hipSuccess; ++k) {
         const Layer &le = L[5 + 3 * k], &ld = L[6 + 3 * k], &lc = L[7 + 3 * k];
+        if (fused) {
+            IrArgs ia{};
+            ia.h_in = net->h[k];
+            ia.h_out = net->h[k + 1];
+            ia.we = net->packs + le.fwd;
+            ia.be = net->params + le.off_b;
+            ia.wd = net->params + ld.off_w;
+            ia.bd = net->params + ld.off_b;
+            ia.wc = net->packs + lc.fwd;
+            ia.bc = net->params + lc.off_b;
+            ia.n = n;
+            ia.Hf = net->Hf;
+            ia.Wf = net->Wf;
+            ia.ch = c.c_hid;
+            ia.x = X;
+            e = launch_ir_block(ia, st);
+            continue;
+        }
         e = launch_pw(pw_args(net, le, nhwc(net->h[k], c.c_hid), none(), HW2, P2, net->u[k]), st);
         if (e == hipSuccess)
             e = launch_dw_fwd(net->u[k], net->params + ld.off_w, net->params + ld.off_b, net->v_[k], n, net->Hf,
@@ -396,8 +421,8 @@ hipError_t run_backward(me_prnet net, const void* zp, hipStream_t st)
     if (e != hipSuccess) return e;
     // projection: input [z_pred, e4]; its gradient reaches e4 only
     const PwTensor dp = nhwc(net->dh[cur], c.c_hid);
-    const PwTensor z{zp, c.c_feat, 1, 1};
-    e = pw_grad(net, L[4], z, nhwc(net->e4, c.c_enc), dp, HW2, P2, st);
+    (void)zp;                                     // the forward pass left z_pred channels-last in net->zl
+    e = pw_grad(net, L[4], nhwc(net->zl, c.c_feat), nhwc(net->e4, c.c_enc), dp, HW2, P2, st);
     if (e == hipSuccess) e = pw_dgrad(net, L[4], dp, HW2, P2, nullptr, net->e4, net->gA, st);              // de4
     if (e == hipSuccess) e = pw_grad(net, L[3], nhwc(net->e3, c.c_enc), none(), nhwc(net->gA, c.c_enc), HW2, P2, st);
     if (e == hipSuccess) e = pw_dgrad(net, L[3], nhwc(net->gA, c.c_enc), HW2, P2, nullptr, net->e3, net->gB, st);  // de3
@@ -596,9 +621,8 @@ me_status me_prnet_dw_backward(me_ctx ctx, const uint16_t* x, const float* w, co
     if (e != hipSuccess) return hip_fail(e, "me_prnet_dw_backward: hipSetDevice");
     hipStream_t st = as_stream(stream);
     if (grads) {
-        const int P = n * osz(H, stride) * osz(W, stride);
         void* part = nullptr;
-        me_status s = ctx_scratch(ctx, dw_partial_floats(P, C) * 4, &part);
+        me_status s = ctx_scratch(ctx, std::max<size_t>(dw_partial_floats(n, H, W, stride, C), 1) * 4, &part);
         if (s != ME_OK) return s;
         e = dw_wgrad(x, dy, static_cast<float*>(part), grads, grads + (size_t)C * 9, n, H, W, C, stride, st);
     }

@@ -456,6 +456,25 @@ def feature_grid(frame_h, frame_w):
     return (((hp - 1) // 2) // 2 + 1, ((wp - 1) // 2) // 2 + 1)
 
 
+def prnet_init_params(cfg: MePrnetCfg, seed: int = 0, head_scale: float = 1.0):
+    """Seeded starting parameters in the library's order: He-normal weights
+    (fan-in 9 for depthwise layers, c_in for 1x1 layers), biases 0.1 before a
+    ReLU6 and 0 otherwise, the head's weights scaled by head_scale."""
+    import numpy as np
+
+    e, h, x = cfg.c_enc, cfg.c_hid, cfg.c_hid * cfg.expand
+    layers = [(9, 4, True), (4, e, True), (9, e, True), (e, e, True), (cfg.c_feat + e, h, True)]
+    for _ in range(cfg.n_blocks):
+        layers += [(h, x, True), (9, x, True), (x, h, False)]
+    layers.append((h, cfg.c_feat, False))
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i, (fan, co, relu) in enumerate(layers):
+        w = rng.normal(0.0, np.sqrt(2.0 / fan), co * fan)
+        parts += [w * (head_scale if i == len(layers) - 1 else 1.0), np.full(co, 0.1 if relu else 0.0)]
+    return np.concatenate(parts).astype(np.float32)
+
+
 class Prnet:
     """A network object of the library (me_prnet_*)."""
 

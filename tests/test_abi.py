@@ -214,3 +214,19 @@ def test_prnet_num_params_and_validation(me):
                                     FAKE, FAKE, None) == me.ME_E_INVAL
     assert me._me_prnet_loss(None, FAKE, FAKE, FAKE, 1, 16, 4, 4, 0.0, FAKE, FAKE, None) == me.ME_E_INVAL
     assert me.feature_grid(1080, 1920) == (135, 240) and me.feature_grid(22, 10) == (3, 2)
+
+
+def test_prnet_init_params_layout(me):
+    """The binding's starting parameters have the library's size and order:
+    depthwise weights of fan-in 9, biases 0.1 before ReLU6 (compared with the
+    oracle's layer table)."""
+    import numpy as np
+
+    from oracle import prnet as P
+
+    cfg = P.Cfg(48, 16, 32, 3, 2)
+    p = me.prnet_init_params(me.MePrnetCfg(48, 16, 32, 3, 2), seed=1)
+    assert p.size == P.n_params(cfg) and p.dtype == np.float32
+    for (W, b), (kind, ci, co, _, act) in zip(P.unpack(p, cfg), P.layer_specs(cfg)):
+        assert np.all(b == (np.float32(0.1) if act else 0.0))
+        assert W.shape == ((co, 9) if kind == "dw" else (co, ci))

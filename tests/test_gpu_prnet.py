@@ -240,14 +240,17 @@ def _net_inputs(seed, n, H, W, cfg):
     return frames, zp, zt
 
 
-@pytest.mark.parametrize("zdtype", ["f32", "bf16"])
-def test_network_forward(dev, ctx, zdtype):
+# (32, 16, 16, 2, 2): expanded width 32, blocks layer by layer; the others have
+# expanded widths that are multiples of 64 and take the fused block kernel.
+@pytest.mark.parametrize("zdtype,cfgt,nimg", [("f32", CFG_SMALL, 2), ("bf16", CFG_SMALL, 2),
+                                              ("f32", (32, 16, 32, 2, 2), 2), ("bf16", (48, 16, 16, 4, 1), 3)])
+def test_network_forward(dev, ctx, zdtype, cfgt, nimg):
     import torch
 
-    cfg = P.Cfg(*CFG_SMALL)
-    frames, zp, _ = _net_inputs(3, 2, 118, 166, cfg)
+    cfg = P.Cfg(*cfgt)
+    frames, zp, _ = _net_inputs(3, nimg, 118, 166, cfg)
     params = P.init_params(cfg, 1)
-    net = dev.Prnet(ctx, dev.MePrnetCfg(*CFG_SMALL))
+    net = dev.Prnet(ctx, dev.MePrnetCfg(*cfgt))
     try:
         net.set_params(params)
         assert np.array_equal(net.get_params(), params)
