@@ -598,7 +598,7 @@ __global__ __launch_bounds__(256) void ir_block_kernel(IrArgs a)
     uint16_t* hl = lds;                                   // [112][CH + 8]   h over tile + halo
     uint16_t* ul = hl + kIrRows * ldh;                     // [112][72]       u, one chunk
     uint16_t* vl = ul + kIrRows * kIrLd;                   // [64][72]        v, one chunk
-    float* wl = reinterpret_cast<float*>(vl + kIrT * kIrT * kIrLd);   // [64][9] depthwise weights, then [64] bias
+    float* wl = reinterpret_cast<float*>(vl + kIrT * kIrT * kIrLd);   // [64][10] depthwise weights + bias, [64] expansion bias
     const int tiles_x = (a.Wf + kIrT - 1) / kIrT, tiles_y = (a.Hf + kIrT - 1) / kIrT;
     const int img = blockIdx.x / (tiles_x * tiles_y), tr = blockIdx.x - img * tiles_x * tiles_y;
     const int y0 = (tr / tiles_x) * kIrT, x0 = (tr % tiles_x) * kIrT;
@@ -618,60 +618,62 @@ __global__ __launch_bounds__(256) void ir_block_kernel(IrArgs a)
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, n = lane & 15;
     const uint2* we = reinterpret_cast<const uint2*>(a.we);
     const uint2* wc = reinterpret_cast<const uint2*>(a.wc);
-    constexpr int KSe = CH >> 4, MTc = CH >> 4;
+    constexpr int KSe = CH >> 4, MTc = CH >> 4, MPW = (MTc + 3) / 4;   // compression row tiles per wave
     const int KSc = X >> 4;
-    // expansion column tiles of this wave: w and w + 4 (tile 7 does not exist)
-    bool inside[2];
+    // Wave w owns expansion row tile w of every chunk (16 of its 64 channels)
+    // and compression row tiles w, w + 4, ...: it loads only those weights and
+    // reuses them across all column (pixel) tiles.
+    v4f32 acc2[MPW][4];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int hp = (w + 4 * j) * 16 + n;
-        const int gy = y0 + hp / kIrHW - 1, gx = x0 + hp % kIrHW - 1;
-        inside[j] = hp < kIrHalo && gy >= 0 && gy < a.Hf && gx >= 0 && gx < a.Wf;
-    }
-    v4f32 acc2[MTc];
+    for (int j = 0; j < MPW; ++j)
 #pragma unroll
-    for (int t = 0; t < MTc; ++t) acc2[t] = (v4f32){0.f, 0.f, 0.f, 0.f};
+        for (int nt = 0; nt < 4; ++nt) acc2[j][nt] = (v4f32){0.f, 0.f, 0.f, 0.f};
     const int c4 = threadIdx.x & 15;                       // channel group of this thread in the depthwise step
 
 #pragma unroll 1
     for (int q = 0; q < X / kIrChunk; ++q) {
+        v4i16 wa[KSe];
+#pragma unroll
+        for (int ks = 0; ks < KSe; ++ks) wa[ks] = as_v4(we[((size_t)(4 * q + w) * KSe + ks) * 64 + lane]);
+        v4i16 wb[MPW][4];
+#pragma unroll
+        for (int j = 0; j < MPW; ++j)
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks)
+                wb[j][ks] = w + 4 * j < MTc ? as_v4(wc[((size_t)(w + 4 * j) * KSc + 4 * q + ks) * 64 + lane])
+                                            : as_v4(make_uint2(0u, 0u));
         __syncthreads();                                   // h staged / previous chunk's u, v and weights read
-        for (int e = threadIdx.x; e < kIrChunk * 10; e += blockDim.x) {
-            const int cc = e / 10, t = e - cc * 10;
-            wl[e] = t < 9 ? a.wd[(q * kIrChunk + cc) * 9 + t] : a.bd[q * kIrChunk + cc];
+        for (int e = threadIdx.x; e < kIrChunk * 11; e += blockDim.x) {
+            const int cc = e / 11, t = e - cc * 11;
+            const int ch = q * kIrChunk + cc;
+            wl[t < 10 ? cc * 10 + t : kIrChunk * 10 + cc] = t < 9 ? a.wd[ch * 9 + t] : (t == 9 ? a.bd[ch] : a.be[ch]);
         }
-        // expand channels [64 q, 64 q + 64) of the halo pixels
+        __syncthreads();
+        // expansion: channels 64 q + 16 w .. + 15 for the 112 halo rows
+        const int oe = 16 * w + 4 * g;
+        const float be0 = wl[kIrChunk * 10 + oe], be1 = wl[kIrChunk * 10 + oe + 1], be2 = wl[kIrChunk * 10 + oe + 2],
+                    be3 = wl[kIrChunk * 10 + oe + 3];
 #pragma unroll 1
-        for (int j = 0; j < 2; ++j) {
-            const int nt = w + 4 * j;
-            if (nt * 16 >= kIrRows) break;
+        for (int nt = 0; nt < kIrRows / 16; ++nt) {
             const int hp = nt * 16 + n;
+            const int gy = y0 + hp / kIrHW - 1, gx = x0 + hp % kIrHW - 1;
+            const bool inside = hp < kIrHalo && gy >= 0 && gy < a.Hf && gx >= 0 && gx < a.Wf;
             const uint16_t* brow = hl + hp * ldh + 4 * g;
-            v4f32 acc[4];
+            v4f32 acc = (v4f32){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int t = 0; t < 4; ++t) acc[t] = (v4f32){0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int ks = 0; ks < KSe; ++ks) {
-                const v4i16 b = as_v4(*reinterpret_cast<const uint2*>(brow + ks * 16));
-#pragma unroll
-                for (int t = 0; t < 4; ++t)
-                    acc[t] = mfma(as_v4(we[((size_t)(4 * q + t) * KSe + ks) * 64 + lane]), b, acc[t]);
-            }
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int o = 16 * t + 4 * g;                    // channel within the chunk
-                float v[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) v[i] = inside[j] ? relu6f(acc[t][i] + a.be[q * kIrChunk + o + i]) : 0.f;
-                *reinterpret_cast<uint2*>(ul + hp * kIrLd + o) = pack4(v[0], v[1], v[2], v[3]);
-            }
+            for (int ks = 0; ks < KSe; ++ks) acc = mfma(wa[ks], as_v4(*reinterpret_cast<const uint2*>(brow + ks * 16)), acc);
+            *reinterpret_cast<uint2*>(ul + hp * kIrLd + oe) =
+                inside ? pack4(relu6f(acc[0] + be0), relu6f(acc[1] + be1), relu6f(acc[2] + be2), relu6f(acc[3] + be3))
+                       : make_uint2(0u, 0u);
         }
         __syncthreads();
         // depthwise: 64 pixels x 16 channel groups, 4 per thread
+        float wk[40];
+#pragma unroll
+        for (int i = 0; i < 40; ++i) wk[i] = wl[4 * c4 * 10 + i];
 #pragma unroll 1
         for (int j = 0; j < 4; ++j) {
             const int px = (threadIdx.x >> 4) + 16 * j, ty = px >> 3, tx = px & 7;
-            const float* wk = wl + 4 * c4 * 10;
             float acc[4] = {wk[9], wk[19], wk[29], wk[39]};
 #pragma unroll
             for (int ky = 0; ky < 3; ++ky)
@@ -689,28 +691,36 @@ __global__ __launch_bounds__(256) void ir_block_kernel(IrArgs a)
                 pack4(relu6f(acc[0]), relu6f(acc[1]), relu6f(acc[2]), relu6f(acc[3]));
         }
         __syncthreads();
-        // compression, column tile w (pixels 16 w .. 16 w + 15)
-        const uint16_t* brow = vl + (w * 16 + n) * kIrLd + 4 * g;
+        // compression: row tiles w + 4 j over the four column tiles (64 pixels)
 #pragma unroll
-        for (int ks = 0; ks < kIrChunk / 16; ++ks) {
-            const v4i16 b = as_v4(*reinterpret_cast<const uint2*>(brow + ks * 16));
+        for (int nt = 0; nt < 4; ++nt) {
+            const uint16_t* brow = vl + (nt * 16 + n) * kIrLd + 4 * g;
 #pragma unroll
-            for (int t = 0; t < MTc; ++t)
-                acc2[t] = mfma(as_v4(wc[((size_t)t * KSc + 4 * q + ks) * 64 + lane]), b, acc2[t]);
+            for (int ks = 0; ks < kIrChunk / 16; ++ks) {
+                const v4i16 b = as_v4(*reinterpret_cast<const uint2*>(brow + ks * 16));
+#pragma unroll
+                for (int j = 0; j < MPW; ++j) acc2[j][nt] = mfma(wb[j][ks], b, acc2[j][nt]);
+            }
         }
     }
 
-    // h_out = h + Wc v + bc at pixel 16 w + n of the tile
-    const int px = w * 16 + n, ty = px >> 3, tx = px & 7, gy = y0 + ty, gx = x0 + tx;
-    if (gy >= a.Hf || gx >= a.Wf) return;
-    const uint16_t* skip = hl + ((ty + 1) * kIrHW + tx + 1) * ldh;
-    uint2* hout = reinterpret_cast<uint2*>(a.h_out) + ((size_t)img * a.Hf * a.Wf + (size_t)gy * a.Wf + gx) * c4n;
+    // h_out = h + Wc v + bc
+    uint2* hout = reinterpret_cast<uint2*>(a.h_out) + (size_t)img * a.Hf * a.Wf * c4n;
 #pragma unroll
-    for (int t = 0; t < MTc; ++t) {
+    for (int j = 0; j < MPW; ++j) {
+        const int t = w + 4 * j;
+        if (t >= MTc) break;
         const int o = t * 16 + 4 * g;
-        const float4 sk = unpack4(*reinterpret_cast<const uint2*>(skip + o));
-        hout[o >> 2] = pack4(acc2[t][0] + a.bc[o] + sk.x, acc2[t][1] + a.bc[o + 1] + sk.y,
-                             acc2[t][2] + a.bc[o + 2] + sk.z, acc2[t][3] + a.bc[o + 3] + sk.w);
+        const float bc0 = a.bc[o], bc1 = a.bc[o + 1], bc2 = a.bc[o + 2], bc3 = a.bc[o + 3];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const int px = nt * 16 + n, ty = px >> 3, tx = px & 7, gy = y0 + ty, gx = x0 + tx;
+            if (gy >= a.Hf || gx >= a.Wf) continue;
+            const float4 sk = unpack4(*reinterpret_cast<const uint2*>(hl + ((ty + 1) * kIrHW + tx + 1) * ldh + o));
+            hout[((size_t)gy * a.Wf + gx) * c4n + (o >> 2)] =
+                pack4(acc2[j][nt][0] + bc0 + sk.x, acc2[j][nt][1] + bc1 + sk.y, acc2[j][nt][2] + bc2 + sk.z,
+                      acc2[j][nt][3] + bc3 + sk.w);
+        }
     }
 }
 
@@ -727,14 +737,21 @@ __global__ __launch_bounds__(256) void to_nhwc_kernel(const void* __restrict__ s
 #pragma unroll
     for (int pass = 0; pass < 4; ++pass) {
         const int r = (threadIdx.x >> 4) + 16 * pass, c = c0 + r;
+        const size_t base = ((size_t)img * C + c) * HW + p0 + col;
+        if (f32 && (HW & 3) == 0 && c < C && p0 + col + 3 < HW) {
+            const float4 v = *reinterpret_cast<const float4*>(static_cast<const float*>(src) + base);
+            t[r][col] = f2bf(v.x);
+            t[r][col + 1] = f2bf(v.y);
+            t[r][col + 2] = f2bf(v.z);
+            t[r][col + 3] = f2bf(v.w);
+            continue;
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int px = p0 + col + i;
             float v = 0.f;
-            if (c < C && px < HW) {
-                const size_t idx = ((size_t)img * C + c) * HW + px;
-                v = f32 ? static_cast<const float*>(src)[idx] : bf2f(static_cast<const uint16_t*>(src)[idx]);
-            }
+            if (c < C && px < HW)
+                v = f32 ? static_cast<const float*>(src)[base + i] : bf2f(static_cast<const uint16_t*>(src)[base + i]);
             t[r][col + i] = f2bf(v);
         }
     }
@@ -1037,7 +1054,7 @@ size_t ir_lds_bytes(int ch, int x)
 {
     (void)x;
     return (size_t)(kIrRows * (ch + 8) + kIrRows * kIrLd + kIrT * kIrT * kIrLd) * sizeof(uint16_t) +
-           kIrChunk * 10 * sizeof(float);
+           kIrChunk * 11 * sizeof(float);
 }
 
 bool ir_fused_ok(int ch, int x)
