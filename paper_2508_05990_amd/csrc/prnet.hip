@@ -147,27 +147,20 @@ __device__ void stage_cols(const PwTensor& t, int koff, int p0, int p1, int HW, 
 
 // ------------------------------------------------------------ 1x1 GEMM --
 
-// One workgroup per 64-pixel tile (grid-stride over tiles); each wave computes
-// 16 pixels for every output channel.  WLDS: the packed weights are copied to
-// LDS once per workgroup and shared by its four waves and all its tiles;
-// otherwise each wave reads them from memory (caches) as it goes.
-template <bool WLDS>
+// One workgroup per 64-pixel tile (grid-stride over tiles).  Wave w owns the
+// output row tiles w, w + 4, ... (16 channels each) for all four 16-pixel
+// column tiles of the tile: it loads each A operand (packed weights) once and
+// applies it to the four column tiles read from LDS.
 __global__ __launch_bounds__(256) void pw_kernel(PwArgs a)
 {
     extern __shared__ __align__(16) uint16_t lds[];
     const int K = a.KS * 16, ldk = K + 8;
     const int MT = (a.M + 15) >> 4;
-    const size_t wwords = WLDS ? (size_t)MT * a.KS * 256 : 0;   // bfloat16 elements of the packed weights
-    uint16_t* xl = lds + wwords;
-    const uint2* wp = WLDS ? reinterpret_cast<const uint2*>(lds) : reinterpret_cast<const uint2*>(a.w);
-    if (WLDS) {
-        const uint4* src = reinterpret_cast<const uint4*>(a.w);
-        uint4* dst = reinterpret_cast<uint4*>(lds);
-        for (int e = threadIdx.x; e < (int)(wwords >> 3); e += blockDim.x) dst[e] = src[e];
-    }
+    uint16_t* xl = lds;
+    const uint2* wp = reinterpret_cast<const uint2*>(a.w);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, n = lane & 15;
     const int ntiles = (a.P + kPx - 1) / kPx;
-    int kc = a.x.C + (a.x2.p ? a.x2.C : 0);
+    const int kc = a.x.C + (a.x2.p ? a.x2.C : 0);
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int p0 = tile * kPx;
         __syncthreads();                                   // the previous tile's reads of xl are done
@@ -179,49 +172,50 @@ __global__ __launch_bounds__(256) void pw_kernel(PwArgs a)
         }
         __syncthreads();
 
-        const uint16_t* brow = xl + (16 * w + n) * ldk + 4 * g;
-        const int p = p0 + 16 * w + n;
-        for (int mt0 = 0; mt0 < MT; mt0 += kNG) {
-            v4f32 acc[kNG];
+        for (int t = w; t < MT; t += 4) {
+            v4f32 acc[4];
 #pragma unroll
-            for (int t = 0; t < kNG; ++t) acc[t] = (v4f32){0.f, 0.f, 0.f, 0.f};
+            for (int nt = 0; nt < 4; ++nt) acc[nt] = (v4f32){0.f, 0.f, 0.f, 0.f};
             for (int ks = 0; ks < a.KS; ++ks) {
-                const v4i16 b = as_v4(*reinterpret_cast<const uint2*>(brow + ks * 16));
+                const v4i16 wa = as_v4(wp[((size_t)t * a.KS + ks) * 64 + lane]);
 #pragma unroll
-                for (int t = 0; t < kNG; ++t)
-                    if (mt0 + t < MT) acc[t] = mfma(as_v4(wp[((size_t)(mt0 + t) * a.KS + ks) * 64 + lane]), b, acc[t]);
+                for (int nt = 0; nt < 4; ++nt)
+                    acc[nt] = mfma(wa, as_v4(*reinterpret_cast<const uint2*>(xl + (nt * 16 + n) * ldk + ks * 16 + 4 * g)),
+                                   acc[nt]);
             }
-            if (p < a.P) {
+            const int o = t * 16 + 4 * g;
+            if (o >= a.M) continue;
+            float bias[4] = {0.f, 0.f, 0.f, 0.f};
+            if (a.bias) {
 #pragma unroll
-                for (int t = 0; t < kNG; ++t) {
-                    if (mt0 + t >= MT) break;
-                    const int o = (mt0 + t) * 16 + 4 * g;
-                    if (o >= a.M) break;
-                    float v[4] = {acc[t][0], acc[t][1], acc[t][2], acc[t][3]};
-                    if (a.bias) {
+                for (int i = 0; i < 4; ++i) bias[i] = a.bias[o + i];
+            }
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) v[i] += a.bias[o + i];
-                    }
-                    if (a.relu6) {
+            for (int nt = 0; nt < 4; ++nt) {
+                const int p = p0 + nt * 16 + n;
+                if (p >= a.P) continue;
+                float v[4];
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) v[i] = relu6f(v[i]);
-                    }
-                    if (a.add.p) {
-                        const float4 d = load4(a.add, p, o, a.HW);
-                        v[0] += d.x;
-                        v[1] += d.y;
-                        v[2] += d.z;
-                        v[3] += d.w;
-                    }
-                    if (a.mask) {
-                        const float4 m = unpack4(*reinterpret_cast<const uint2*>(a.mask + (size_t)p * a.M + o));
-                        v[0] *= keep(m.x);
-                        v[1] *= keep(m.y);
-                        v[2] *= keep(m.z);
-                        v[3] *= keep(m.w);
-                    }
-                    store4(a.out, a.out_chw, a.out_f32, a.M, a.HW, p, o, make_float4(v[0], v[1], v[2], v[3]));
+                for (int i = 0; i < 4; ++i) v[i] = acc[nt][i] + bias[i];
+                if (a.relu6) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) v[i] = relu6f(v[i]);
                 }
+                if (a.add.p) {
+                    const float4 d = load4(a.add, p, o, a.HW);
+                    v[0] += d.x;
+                    v[1] += d.y;
+                    v[2] += d.z;
+                    v[3] += d.w;
+                }
+                if (a.mask) {
+                    const float4 m = unpack4(*reinterpret_cast<const uint2*>(a.mask + (size_t)p * a.M + o));
+                    v[0] *= keep(m.x);
+                    v[1] *= keep(m.y);
+                    v[2] *= keep(m.z);
+                    v[3] *= keep(m.w);
+                }
+                store4(a.out, a.out_chw, a.out_f32, a.M, a.HW, p, o, make_float4(v[0], v[1], v[2], v[3]));
             }
         }
     }
@@ -925,26 +919,14 @@ static hipError_t allow_lds(const void* k, size_t bytes)
     return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-constexpr size_t kPwWeightsLds = 96 * 1024;   // packed weights up to this size go to LDS
-
 hipError_t launch_pw(const PwArgs& a, hipStream_t st)
 {
     if (a.P <= 0) return hipSuccess;
-    const size_t wbytes = (size_t)((a.M + 15) >> 4) * a.KS * 512;
     const int ntiles = div_up(a.P, kPx);
-    if (wbytes <= kPwWeightsLds && wbytes + pw_lds_bytes(a.KS) <= 158 * 1024) {
-        const size_t lds = wbytes + pw_lds_bytes(a.KS);
-        hipError_t e = allow_lds(reinterpret_cast<const void*>(pw_kernel<true>), lds);
-        if (e != hipSuccess) return e;
-        // several tiles per workgroup amortise the weight copy once the chip is full
-        const int grid = ntiles < 1024 ? ntiles : 1024;
-        hipLaunchKernelGGL(pw_kernel<true>, dim3(grid), dim3(256), lds, st, a);
-    } else {
-        const size_t lds = pw_lds_bytes(a.KS);
-        hipError_t e = allow_lds(reinterpret_cast<const void*>(pw_kernel<false>), lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(pw_kernel<false>, dim3(ntiles), dim3(256), lds, st, a);
-    }
+    const size_t lds = pw_lds_bytes(a.KS);
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(pw_kernel), lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(pw_kernel, dim3(ntiles < 2048 ? ntiles : 2048), dim3(256), lds, st, a);
     return hipGetLastError();
 }
 
