@@ -147,6 +147,15 @@ __device__ void stage_cols(const PwTensor& t, int koff, int p0, int p1, int HW, 
 
 // ------------------------------------------------------------ 1x1 GEMM --
 
+constexpr int kScLd = kPx + 4;   // row length (floats) of a wave's transpose slice
+
+// Channels-first output through the per-wave LDS transpose: four-pixel groups
+// never straddle two images when HW is a multiple of 4.
+__host__ __device__ inline bool pw_chw_fast(const PwArgs& a)
+{
+    return a.out_chw && (a.HW & 3) == 0 && !a.mask && (!a.add.p || a.add.chw);
+}
+
 // One workgroup per 64-pixel tile (grid-stride over tiles).  Wave w owns the
 // output row tiles w, w + 4, ... (16 channels each) for all four 16-pixel
 // column tiles of the tile: it loads each A operand (packed weights) once and
@@ -161,6 +170,8 @@ __global__ __launch_bounds__(256) void pw_kernel(PwArgs a)
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, n = lane & 15;
     const int ntiles = (a.P + kPx - 1) / kPx;
     const int kc = a.x.C + (a.x2.p ? a.x2.C : 0);
+    const bool chw_fast = pw_chw_fast(a);
+    float* sc = reinterpret_cast<float*>(xl + kPx * ldk) + w * 16 * kScLd;
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int p0 = tile * kPx;
         __syncthreads();                                   // the previous tile's reads of xl are done
@@ -184,12 +195,49 @@ __global__ __launch_bounds__(256) void pw_kernel(PwArgs a)
                                    acc[nt]);
             }
             const int o = t * 16 + 4 * g;
-            if (o >= a.M) continue;
             float bias[4] = {0.f, 0.f, 0.f, 0.f};
-            if (a.bias) {
+            if (a.bias && o < a.M) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) bias[i] = a.bias[o + i];
             }
+            if (chw_fast) {
+                // channels-first output: transpose the 16 x 64 tile through this wave's LDS
+                // slice so that each lane reads/writes four consecutive pixels of one channel
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const float v = acc[nt][i] + bias[i];
+                        sc[(4 * g + i) * kScLd + nt * 16 + n] = a.relu6 ? relu6f(v) : v;
+                    }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int idx = lane + 64 * r, ch = idx >> 4, q4 = idx & 15;
+                    const int oc = t * 16 + ch, px = p0 + 4 * q4;
+                    if (oc >= a.M || px >= a.P) continue;
+                    float4 v = *reinterpret_cast<const float4*>(sc + ch * kScLd + 4 * q4);
+                    const int img = px / a.HW, hw = px - img * a.HW;
+                    const size_t gi = ((size_t)img * a.M + oc) * a.HW + hw;
+                    if (a.add.p) {
+                        const float4 d = a.add.f32 ? *reinterpret_cast<const float4*>(static_cast<const float*>(a.add.p) + gi)
+                                                   : unpack4(*reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(a.add.p) + gi));
+                        v.x += d.x;
+                        v.y += d.y;
+                        v.z += d.z;
+                        v.w += d.w;
+                    }
+                    if (a.out_f32) *reinterpret_cast<float4*>(static_cast<float*>(a.out) + gi) = v;
+                    else *reinterpret_cast<uint2*>(static_cast<uint16_t*>(a.out) + gi) = pack4(v.x, v.y, v.z, v.w);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                continue;
+            }
+            if (o >= a.M) continue;
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt) {
                 const int p = p0 + nt * 16 + n;
@@ -923,7 +971,7 @@ hipError_t launch_pw(const PwArgs& a, hipStream_t st)
 {
     if (a.P <= 0) return hipSuccess;
     const int ntiles = div_up(a.P, kPx);
-    const size_t lds = pw_lds_bytes(a.KS);
+    const size_t lds = pw_lds_bytes(a.KS) + (pw_chw_fast(a) ? 4 * 16 * kScLd * sizeof(float) : 0);
     hipError_t e = allow_lds(reinterpret_cast<const void*>(pw_kernel), lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(pw_kernel, dim3(ntiles < 2048 ? ntiles : 2048), dim3(256), lds, st, a);

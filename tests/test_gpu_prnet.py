@@ -141,14 +141,15 @@ def test_pw_forward_nhwc(dev, ctx, n, HW, cin, cout):
             _close(got, ref, absterm, (relu6, use_add, use_mask))
 
 
-@pytest.mark.parametrize("zdtype", ["f32", "bf16"])
-def test_pw_forward_concat_and_channels_first(dev, ctx, zdtype):
+@pytest.mark.parametrize("zdtype,Hf,Wf", [("f32", 9, 23), ("bf16", 9, 23), ("f32", 8, 23), ("bf16", 12, 5)])
+def test_pw_forward_concat_and_channels_first(dev, ctx, zdtype, Hf, Wf):
     """The projection's input [z_pred (channels-first), encoder (channels-last)]
-    and the head's channels-first output with z_pred added."""
+    and the head's channels-first output with z_pred added (pixels per image a
+    multiple of 4 or not: two store paths)."""
     import torch
 
     rng = np.random.default_rng(5)
-    n, Hf, Wf, Cz, Ce, Ch = 2, 9, 23, 48, 16, 32
+    n, Cz, Ce, Ch = 2, 48, 16, 32
     HW = Hf * Wf
     z = rng.normal(size=(n, Cz, HW))
     if zdtype == "bf16":
