@@ -189,7 +189,8 @@ hipError_t launch_ir_block(const IrArgs& a, hipStream_t st);
 hipError_t launch_to_nhwc(const void* src, int f32, int n, int C, int HW, uint16_t* dst, hipStream_t st);
 int prloss_blocks(int P);
 hipError_t launch_prloss(const float* r, const float* zp, const float* zt, int n, int C, int HW, float tau,
-                         int32_t* nbad, uint32_t* maxbits, uint16_t* dr, float* partial, float* loss, hipStream_t st);
+                         int32_t* nbad, uint32_t* maxbits, uint8_t* flags, uint16_t* dr, float* partial, float* loss,
+                         hipStream_t st);
 
 hipError_t launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t stream);
 hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t stream);

@@ -31,7 +31,7 @@ namespace {
 constexpr int kPx = 64;       // pixels per GEMM workgroup
 constexpr int kNG = 8;        // output-channel tiles per accumulation pass
 constexpr int kTPW = 16;      // weight-gradient tiles per wave
-constexpr int kLdp = kPx + 8; // LDS row length (bfloat16) of channel-major tiles
+constexpr int kLdp = kPx + 4; // LDS row length (bfloat16) of channel-major tiles (8-byte aligned rows)
 
 inline int div_up(int a, int b) { return (a + b - 1) / b; }
 
@@ -112,9 +112,13 @@ __device__ void stage_rows(const PwTensor& t, int koff, int p0, int P, int HW, u
 __device__ void stage_cols(const PwTensor& t, int koff, int p0, int p1, int HW, uint16_t* lds)
 {
     if (!t.chw) {
-        const int c4n = t.C >> 2;
-        for (int e = threadIdx.x; e < kPx * c4n; e += blockDim.x) {
-            const int px = e / c4n, c4 = e - px * c4n, p = p0 + px;
+        // a wave covers 16 channel groups x 4 pixels: 128-byte global segments, and
+        // its transposed LDS writes spread over 16 banks (4-way) with the 68-element rows
+        const int c4n = t.C >> 2, cb = (c4n + 15) >> 4;
+        for (int e = threadIdx.x; e < kPx * cb * 16; e += blockDim.x) {
+            const int hi = e >> 4, c4 = (hi % cb) * 16 + (e & 15), px = hi / cb;
+            if (c4 >= c4n) continue;
+            const int p = p0 + px;
             float4 f = make_float4(0.f, 0.f, 0.f, 0.f);
             uint2 v = make_uint2(0u, 0u);
             if (p < p1) {
@@ -590,8 +594,9 @@ __global__ __launch_bounds__(256) void dw_wgrad_kernel(const uint16_t* __restric
 }
 
 // Sums of partial rows in a fixed order: element e (< m) of the output is
-// sum over rows x of partial[x * stride + e], taken as four interleaved
-// running sums (rows x = q mod 4, in order) added in q order.  mode 0: out[e];
+// sum over rows x of partial[x * stride + e].  Thread group q (of 4) takes rows
+// x = q mod 4 into four running sums by (x / 4) mod 4 (independent loads in
+// flight), adds them in order, and the four groups are added in q order.  mode 0: out[e];
 // mode 1 (depthwise layout [c][10]): tap < 9 -> gw[c*9 + tap], tap 9 -> gb[c].
 __global__ __launch_bounds__(256) void reduce_rows_kernel(const float* __restrict__ partial, int nrows, size_t stride,
                                                           int m, int mode, float* __restrict__ gw,
@@ -600,10 +605,16 @@ __global__ __launch_bounds__(256) void reduce_rows_kernel(const float* __restric
     __shared__ float red[4][64];
     const int j = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int e = blockIdx.x * 64 + j;
-    float s = 0.f;
-    if (e < m)
-        for (int x = q; x < nrows; x += 4) s += partial[(size_t)x * stride + e];
-    red[q][j] = s;
+    float s4[4] = {0.f, 0.f, 0.f, 0.f};
+    if (e < m) {
+        int x = q;
+        for (; x + 12 < nrows; x += 16) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) s4[r] += partial[(size_t)(x + 4 * r) * stride + e];
+        }
+        for (int r = 0; x < nrows; x += 4, ++r) s4[r] += partial[(size_t)x * stride + e];
+    }
+    red[q][j] = ((s4[0] + s4[1]) + s4[2]) + s4[3];
     __syncthreads();
     if (q != 0 || e >= m) return;
     const float t = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
@@ -836,51 +847,61 @@ __device__ __forceinline__ float wave_max(float v)
     return v;
 }
 
-// Per position p: s = sum_c |t|, t = z_target - z_pred; bad = tau >= 0 and s / C > tau.
-// Counts bad positions and takes max |r - t| (order-free, so exact).
+// Blocks of 64 positions x 4 channel quarters (a wave per quarter: 64
+// consecutive positions, so every channel row is read 256 bytes at a time).
+// Pass 1: per position p, s = sum_c |t| (t = z_target - z_pred, quarters added
+// in order); bad = tau >= 0 and s / C > tau (flag stored); counts bad
+// positions and takes max |r - t| (order-free, so exact).
 __global__ __launch_bounds__(256) void prloss_stats_kernel(const float* __restrict__ r, const float* __restrict__ zp,
                                                            const float* __restrict__ zt, int n, int C, int HW,
                                                            float tau, int32_t* __restrict__ nbad,
-                                                           uint32_t* __restrict__ maxbits)
+                                                           uint32_t* __restrict__ maxbits, uint8_t* __restrict__ flags)
 {
+    __shared__ float ss[4][64];
     __shared__ float wm[4];
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    float mx = 0.f;
-    int bad = 0;
-    if (p < n * HW) {
+    const int j = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int P = n * HW, p = blockIdx.x * 64 + j;
+    float s = 0.f, mx = 0.f;
+    if (p < P) {
         const int img = p / HW, hw = p - img * HW;
         const size_t base = (size_t)img * C * HW + hw;
-        float s = 0.f;
-#pragma unroll 8
-        for (int c = 0; c < C; ++c) {
+        const int c0 = q * C / 4, c1 = (q + 1) * C / 4;
+#pragma unroll 4
+        for (int c = c0; c < c1; ++c) {
             const size_t i = base + (size_t)c * HW;
             const float t = zt[i] - zp[i];
             s += fabsf(t);
             mx = fmaxf(mx, fabsf(r[i] - t));
         }
-        bad = tau >= 0.f && s / (float)C > tau;
+    }
+    ss[q][j] = s;
+    mx = wave_max(mx);
+    if (j == 0) wm[q] = mx;
+    __syncthreads();
+    int bad = 0;
+    if (q == 0 && p < P) {
+        bad = tau >= 0.f && (((ss[0][j] + ss[1][j]) + ss[2][j]) + ss[3][j]) / (float)C > tau;
+        flags[p] = (uint8_t)bad;
     }
     const int cnt = __syncthreads_count(bad);
-    mx = wave_max(mx);
-    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = mx;
-    __syncthreads();
     if (threadIdx.x == 0) {
-        const float m = fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]));
         if (cnt) atomicAdd(nbad, cnt);
-        atomicMax(maxbits, __float_as_uint(m));
+        atomicMax(maxbits, __float_as_uint(fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]))));
     }
 }
 
-// Loss terms and dr = dloss/dr (bfloat16, [n][C][HW]); partial[block] = the block's loss, summed in thread order.
+// Pass 2: loss terms and dr = dloss/dr (bfloat16, [n][C][HW]); partial[block] =
+// the block's loss, summed in a fixed tree order.
 __global__ __launch_bounds__(256) void prloss_grad_kernel(const float* __restrict__ r, const float* __restrict__ zp,
                                                           const float* __restrict__ zt, int n, int C, int HW, float tau,
                                                           const int32_t* __restrict__ nbad,
                                                           const uint32_t* __restrict__ maxbits,
-                                                          uint16_t* __restrict__ dr, float* __restrict__ partial)
+                                                          const uint8_t* __restrict__ flags, uint16_t* __restrict__ dr,
+                                                          float* __restrict__ partial)
 {
     __shared__ float red[256];
-    const int P = n * HW;
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int P = n * HW, p = blockIdx.x * 64 + j;
     const float cth = 0.2f * __uint_as_float(*maxbits);
     const int nb = *nbad, ng = P - nb;
     float lsum = 0.f;
@@ -888,18 +909,11 @@ __global__ __launch_bounds__(256) void prloss_grad_kernel(const float* __restric
         const int img = p / HW, hw = p - img * HW;
         const size_t base = (size_t)img * C * HW + hw;
         float wpos = 1.f / (float)P;
-        if (tau >= 0.f && nb > 0 && ng > 0) {
-            float s = 0.f;
-    #pragma unroll 8
-        for (int c = 0; c < C; ++c) {
-                const size_t i = base + (size_t)c * HW;
-                s += fabsf(zt[i] - zp[i]);
-            }
-            wpos = (s / (float)C > tau) ? 0.5f / (float)nb : 0.5f / (float)ng;
-        }
+        if (tau >= 0.f && nb > 0 && ng > 0) wpos = flags[p] ? 0.5f / (float)nb : 0.5f / (float)ng;
         const float wgt = wpos / (float)C;
-#pragma unroll 8
-        for (int c = 0; c < C; ++c) {
+        const int c0 = q * C / 4, c1 = (q + 1) * C / 4;
+#pragma unroll 4
+        for (int c = c0; c < c1; ++c) {
             const size_t i = base + (size_t)c * HW;
             const float x = r[i] - (zt[i] - zp[i]);
             const float a = fabsf(x);
@@ -920,8 +934,8 @@ __global__ __launch_bounds__(256) void prloss_grad_kernel(const float* __restric
     }
     red[threadIdx.x] = lsum;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
         __syncthreads();
     }
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
@@ -1045,10 +1059,11 @@ hipError_t launch_dw_dgrad(const uint16_t* dy, const float* w, const uint16_t* m
     return hipGetLastError();
 }
 
+// Three workgroups per CU (42 KB of LDS each) over 256 CUs.
 int dw_wgrad_nwg(int n, int Ho, int Wo)
 {
     const int U = n * Ho * div_up(Wo, kRun);
-    return U < 256 ? U : 256;
+    return U < 768 ? U : 768;
 }
 
 hipError_t launch_dw_wgrad(const uint16_t* x, const uint16_t* dy, float* partial, float* gw, float* gb, int n, int H,
@@ -1118,18 +1133,20 @@ hipError_t launch_to_nhwc(const void* src, int f32, int n, int C, int HW, uint16
     return hipGetLastError();
 }
 
-int prloss_blocks(int P) { return div_up(P, 256); }
+int prloss_blocks(int P) { return div_up(P, 64); }
 
 hipError_t launch_prloss(const float* r, const float* zp, const float* zt, int n, int C, int HW, float tau,
-                         int32_t* nbad, uint32_t* maxbits, uint16_t* dr, float* partial, float* loss, hipStream_t st)
+                         int32_t* nbad, uint32_t* maxbits, uint8_t* flags, uint16_t* dr, float* partial, float* loss,
+                         hipStream_t st)
 {
     const int P = n * HW, nb = prloss_blocks(P);
     hipError_t e = launch_fill_i32(nbad, 1, 0, st);
     if (e == hipSuccess) e = launch_fill_i32(reinterpret_cast<int32_t*>(maxbits), 1, 0, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(prloss_stats_kernel, dim3(nb), dim3(256), 0, st, r, zp, zt, n, C, HW, tau, nbad, maxbits);
-    hipLaunchKernelGGL(prloss_grad_kernel, dim3(nb), dim3(256), 0, st, r, zp, zt, n, C, HW, tau, nbad, maxbits, dr,
-                       partial);
+    hipLaunchKernelGGL(prloss_stats_kernel, dim3(nb), dim3(256), 0, st, r, zp, zt, n, C, HW, tau, nbad, maxbits,
+                       flags);
+    hipLaunchKernelGGL(prloss_grad_kernel, dim3(nb), dim3(256), 0, st, r, zp, zt, n, C, HW, tau, nbad, maxbits, flags,
+                       dr, partial);
     hipLaunchKernelGGL(prloss_sum_kernel, dim3(1), dim3(256), 0, st, partial, nb, loss);
     return hipGetLastError();
 }

@@ -99,7 +99,7 @@ me_status grow(void** p, size_t* cap, size_t bytes)
     return ME_OK;
 }
 
-constexpr int kWgTarget = 256;   // workgroups of a weight-gradient reduction
+constexpr int kWgTarget = 512;   // workgroups of a weight-gradient reduction
 
 size_t pw_partial_floats(int P, int cin, int cout)
 {
@@ -147,6 +147,7 @@ struct me_prnet_s {
     int32_t* nbad;
     uint32_t* maxbits;
     float* lpart;
+    uint8_t* flags;
     ~me_prnet_s()
     {
         (void)hipSetDevice(device);
@@ -211,6 +212,7 @@ me_status layout(me_prnet net, int n, int Hp, int Wp, bool train)
         sz.push_back(P2 * c.c_hid * 2);          // dh[1]
         sz.push_back(16);                        // nbad, maxbits
         sz.push_back((size_t)prloss_blocks((int)P2) * 4);
+        sz.push_back(P2);                        // loss flags
     }
     size_t total = 0;
     for (size_t s : sz) total += (s + 255) & ~(size_t)255;
@@ -246,6 +248,7 @@ me_status layout(me_prnet net, int n, int Hp, int Wp, bool train)
         net->nbad = (int32_t*)q;
         net->maxbits = (uint32_t*)(q + 4);
         net->lpart = (float*)take();
+        net->flags = (uint8_t*)take();
         size_t pf = 0;
         // partials: the largest layer reduction
         pf = std::max(pf, dw_partial_floats(n, Hp, Wp, 2, 4));
@@ -555,8 +558,8 @@ me_status me_prnet_train_step(me_prnet net, const me_frame* cur, int32_t n, int6
     const int HW2 = net->Hf * net->Wf;
     e = run_forward(net, cur, frame_stride, z_pred, 0, nullptr, true, st);
     if (e == hipSuccess)
-        e = launch_prloss(net->r, z_pred, z_target, n, net->cfg.c_feat, HW2, tau, net->nbad, net->maxbits, net->dr,
-                          net->lpart, loss, st);
+        e = launch_prloss(net->r, z_pred, z_target, n, net->cfg.c_feat, HW2, tau, net->nbad, net->maxbits, net->flags,
+                          net->dr, net->lpart, loss, st);
     if (e == hipSuccess) e = run_backward(net, z_pred, st);
     if (e == hipSuccess && grads) e = hipMemcpyAsync(grads, net->grads, net->np * 4, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess && update) {
@@ -741,11 +744,12 @@ me_status me_prnet_loss(me_ctx ctx, const float* r, const float* z_pred, const f
     if (e != hipSuccess) return hip_fail(e, "me_prnet_loss: hipSetDevice");
     const int P = n * Hf * Wf;
     void* scr = nullptr;
-    me_status s = ctx_scratch(ctx, 256 + (size_t)prloss_blocks(P) * 4, &scr);
+    const size_t pb = ((size_t)prloss_blocks(P) * 4 + 255) & ~(size_t)255;
+    me_status s = ctx_scratch(ctx, 256 + pb + (size_t)P, &scr);
     if (s != ME_OK) return s;
     uint8_t* q = static_cast<uint8_t*>(scr);
     e = launch_prloss(r, z_pred, z_target, n, C, Hf * Wf, tau, reinterpret_cast<int32_t*>(q),
-                      reinterpret_cast<uint32_t*>(q + 4), dr, reinterpret_cast<float*>(q + 256), loss,
+                      reinterpret_cast<uint32_t*>(q + 4), q + 256 + pb, dr, reinterpret_cast<float*>(q + 256), loss,
                       as_stream(stream));
     return e == hipSuccess ? ME_OK : hip_fail(e, "me_prnet_loss");
 }
