@@ -295,6 +295,17 @@ def prnet_leg(me, ctx, frames, z, mvs, B, H, W, args):
         torch.cuda.synchronize()
         ms8 = e0.elapsed_time(e1) / max(2, reps // 4) / n8
         del cur8, z8, out8
+        # the paper's per-frame video path: ME against the previous frame, warp, correction
+        from paper_2508_05990_amd import gop
+
+        gop_frames = frames[:12]
+        gop.propagate(ctx, gop_frames, z, "previous", B, 32, net=net)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(max(1, args.steps // 4)):
+            gop.propagate(ctx, gop_frames, z, "previous", B, 32, net=net)
+        torch.cuda.synchronize()
+        pipe_ms = (time.perf_counter() - t0) * 1e3 / (max(1, args.steps // 4) * (len(gop_frames) - 1))
         nb = 4
         curb = torch.stack(frames[1:1 + nb])
         zpb = torch.stack([me.warp_features(z, mvs[k], B, H, W, ctx=ctx) for k in range(nb)])
@@ -315,7 +326,10 @@ def prnet_leg(me, ctx, frames, z, mvs, B, H, W, args):
             "params": net.n_params, "forward_ms": round(ms, 4), "frames_per_s": round(1e3 / ms, 1),
             "forward_ms_per_frame_batch8": round(ms8, 4), "schedule_bytes": nbytes, "compulsory_bytes": ncomp,
             "achieved_gbs": round(nbytes / ms / 1e6, 1), "hbm_frac": round(nbytes / ms / 1e6 / 8000.0, 4),
-            "hbm_frac_batch8": round(nbytes / ms8 / 1e6 / 8000.0, 4), "train_step_ms_batch4": round(train_ms, 3)}
+            "hbm_frac_batch8": round(nbytes / ms8 / 1e6 / 8000.0, 4), "train_step_ms_batch4": round(train_ms, 3),
+            "video_path_ms_per_frame": round(pipe_ms, 4),
+            "video_path": "GOP of 12: full search B=16 R=32 vs the previous frame, warp of the corrected "
+                          "features, correction by the network"}
 
 
 def batched_leg(me, ctx, args):

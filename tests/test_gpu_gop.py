@@ -75,3 +75,44 @@ def test_schedules_match_oracle(dev, oracle_mod, schedule):
             z_prev = got
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("schedule", ["key", "previous"])
+def test_corrected_propagation_matches_oracle(dev, oracle_mod, schedule):
+    """The paper's video path per frame: ME, warp, correction by the residual
+    network (Sec. 3.3), against the oracle's full search, float64 warp and
+    float64 network (bfloat16 roundings where the kernels store them)."""
+    import torch
+
+    from oracle import prnet as P
+    from paper_2508_05990_amd import gop, synth
+
+    seq = synth.sequence(23, H=256, W=384, n_frames=4, n_rects=3, side=(24, 64), vmax=8)
+    H, W = seq.shape
+    B, R = 16, 16
+    cfgt = (32, 16, 16, 4, 1)
+    cfg = P.Cfg(*cfgt)
+    Hf, Wf = P.feature_grid(H // 2, W // 2)
+    z0 = synth.features(6, cfg.c_feat, Hf, Wf)
+    params = P.init_params(cfg, 4, head_scale=0.2)
+    frames = [_to_dev(f) for f in seq.frames]
+    ctx = dev.Context(0)
+    net = dev.Prnet(ctx, dev.MePrnetCfg(*cfgt))
+    try:
+        net.set_params(params)
+        feats, _ = gop.propagate(ctx, frames, _to_dev(z0), schedule, B, R, net=net)
+        torch.cuda.synchronize()
+        z_prev = z0.astype(np.float64)
+        for t in range(1, len(frames)):
+            ref = seq.frames[0] if schedule == "key" else seq.frames[t - 1]
+            mv, _, _ = oracle_mod.full_search(ref, seq.frames[t], B, R)
+            src = z_prev if schedule == "previous" else z0
+            zw, _ = oracle_mod.warp_features(src, mv, B, H // 2, W // 2)
+            _, r, zo = P.forward(params, cfg, seq.frames[t], zw[None])
+            got = feats[t - 1].cpu().numpy().astype(np.float64)
+            rel = np.linalg.norm(got - zo[0]) / np.linalg.norm(zo[0])
+            assert rel < 1e-2, (t, rel)
+            z_prev = zo[0]
+    finally:
+        net.close()
+        ctx.close()
