@@ -70,7 +70,13 @@ def cpu_baseline(frames, feats, B, R, budget_s):
         el = time.perf_counter() - t0
         if el >= budget_s or n + 1 >= len(frames):
             break
-    return {"value": n / el, "unit": "frames/s", "cores": cores, "kind": "oracle",
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": n / el, "unit": "frames/s", "cores": cores, "kind": "oracle", "cpu_model": model,
             "sample": "%d consecutive 1080p pairs, full search B=%d R=%d over all blocks + float64 warp of "
                       "[%d,%d,%d], %.1f s" % (n, B, R, *feats.shape, el)}
 
@@ -332,6 +338,44 @@ def prnet_leg(me, ctx, frames, z, mvs, B, H, W, args):
                           "features, correction by the network"}
 
 
+def paper_shapes_leg(me, ctx, args):
+    """Like-for-like context for the paper's runtimes (Sec. 4.2): one frame pair
+    at the CamVid (720x960) and Cityscapes (1024x2048) Bayer shapes, synthetic
+    content of the 1080p recipe; full search +-32 and the coarse-to-fine
+    pyramid (standard setting), ms per pair.  The paper's numbers are the
+    standard FME on an A100: context, not a target."""
+    import numpy as np
+    import torch
+
+    from paper_2508_05990_amd import synth
+
+    out = {}
+    for name, (H, W), paper_ms in (("camvid_720x960", (720, 960), 3.36), ("cityscapes_1024x2048", (1024, 2048), 4.44)):
+        seq = synth.sequence(31, H=H, W=W, n_frames=2, n_rects=6, side=(32, 128), vmax=16)
+        f0, f1 = (torch.from_numpy(f).cuda() for f in seq.frames)
+        bh, bw = me.block_grid(H, W, 16)
+        mv = torch.empty((bh, bw, 2), dtype=torch.int16, device="cuda")
+        sad = torch.empty((bh, bw), dtype=torch.int32, device="cuda")
+        params = me.make_params(16, 32)
+        cfg = me.pyramid_cfg((32, 16), ((8, 8), (4, 4), (2, 1)), 127)
+        res = {"paper_fme_standard_ms_a100": paper_ms}
+        for label, fn in (("full_search_r32_ms", lambda: me.estimate(f0, f1, mv=mv, sad=sad, params=params, ctx=ctx)),
+                          ("pyramid_standard_ms", lambda: me.pyramid(f0, f1, ctx, cfg, mv=mv, sad=sad))):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = max(10, args.steps)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            res[label] = round(e0.elapsed_time(e1) / reps, 4)
+        out[name] = res
+    return out
+
+
 def batched_leg(me, ctx, args):
     """24 independent streams of 8 frames (640x480 to 3840x2160, (B, R) in
     {8, 16} x {16, 32}): 168 pairs as one graph-captured persistent launch
@@ -453,6 +497,7 @@ def main():
     ap.add_argument("--no-pyramid", action="store_true", help="skip the pyramid-search measurement")
     ap.add_argument("--no-gop", action="store_true", help="skip the group-of-pictures propagation measurement")
     ap.add_argument("--no-prnet", action="store_true", help="skip the residual-network measurement")
+    ap.add_argument("--no-paper-shapes", action="store_true", help="skip the paper-shape context measurement")
     ap.add_argument("--uhd-frames", type=int, default=16, help="frames of the 4K sequence (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes (reference for HBM byte counters)")
@@ -552,6 +597,9 @@ def main():
         "warp_us_per_pair": round(warp_avg * 1e3, 3),
         "warp_gbs": round(warp_bytes / (warp_avg * 1e-3) / 1e9, 1),
         "warp_hbm_frac": round(warp_bytes / (warp_avg * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+        # whole step against its roofline: SAD-ops at the integer peak plus warp bytes at 8 TB/s, per pair
+        "step_roofline_frac": round((ops / (PEAK_SAD_TOPS * 1e12) + warp_bytes / (PEAK_HBM_GBS * 1e9))
+                                    / (wall / (npairs * args.steps)), 4),
     }
     if not args.no_proposal:
         res["proposal"] = proposal_leg(me, ctx, frames, mvs, z, outs, B, R, H, W, args)
@@ -561,6 +609,8 @@ def main():
         res["gop_propagation"] = gop_leg(me, ctx, frames, B, R, args)
     if not args.no_prnet:
         res["prnet"] = prnet_leg(me, ctx, frames, z, mvs, B, H, W, args)
+    if not args.no_paper_shapes:
+        res["paper_shapes"] = paper_shapes_leg(me, ctx, args)
     if not args.no_batched:
         res["batched_streams"] = batched_leg(me, ctx, args)
     if args.uhd_frames > 1:
