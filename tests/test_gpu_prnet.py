@@ -368,3 +368,45 @@ def test_training_reduces_loss(dev, ctx):
         assert float(loss.item()) < 0.9 * first, (first, float(loss.item()))
     finally:
         net.close()
+
+
+@pytest.mark.parametrize("cfgt", [(16, 16, 16, 1, 0), (32, 16, 48, 4, 1), (16, 32, 32, 3, 2)])
+def test_train_step_other_shapes(dev, ctx, cfgt):
+    """No residual block (the head's input gradient carries the projection's
+    mask), a fused-width hidden layer of 48 channels, an expansion of 3 (96
+    channels, layer by layer at inference): gradients against the oracle;
+    frames with a padded pitch and a frame stride larger than the frame."""
+    import torch
+
+    cfg = P.Cfg(*cfgt)
+    frames, zp, zt = _net_inputs(11, 2, 86, 134, cfg)
+    n, H, W = frames.shape
+    padded = np.zeros((n, H + 3, W + 10), np.uint16)
+    padded[:, :H, :W] = frames
+    buf = torch.from_numpy(padded).cuda()
+    cur = buf[:, :H, :W]                                   # pitch W + 10, frame stride (H + 3)(W + 10)
+    params = P.init_params(cfg, 5, head_scale=0.3)
+    net = dev.Prnet(ctx, dev.MePrnetCfg(*cfgt))
+    try:
+        net.set_params(params)
+        grads = torch.empty(net.n_params, dtype=torch.float32, device="cuda")
+        loss = net.train_step(cur, _f32(zp), _f32(zt), tau=0.1, update=False, grads=grads)
+        out = net.forward(cur, _f32(zp))
+        torch.cuda.synchronize()
+        A, r, zo = P.forward(params, cfg, frames, zp)
+        L, dr, _ = P.loss_and_grad(r, zp, zt, 0.1)
+        assert float(loss.item()) == pytest.approx(L, rel=2e-2)
+        rel = np.linalg.norm((_host(out) - zp) - r) / np.linalg.norm(r)
+        assert rel < 2e-2, rel
+        g_ref = P.backward(params, cfg, A, dr)
+        g = grads.cpu().numpy().astype(np.float64)
+        k = 0
+        for i, (W_, b_) in enumerate(P.unpack(params, cfg)):
+            for part in (W_, b_):
+                a, bb = g[k:k + part.size], g_ref[k:k + part.size]
+                k += part.size
+                relg = np.linalg.norm(a - bb) / max(np.linalg.norm(bb), 1e-30)
+                cos = a @ bb / max(np.linalg.norm(a) * np.linalg.norm(bb), 1e-30)
+                assert relg < 5e-2 and cos > 0.998, (i, relg, cos)
+    finally:
+        net.close()
