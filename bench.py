@@ -338,6 +338,40 @@ def prnet_leg(me, ctx, frames, z, mvs, B, H, W, args):
                           "features, correction by the network"}
 
 
+def fused_leg(me, ctx, frames, z, mvs, sads, outs, B, R, H, W, args):
+    """The same step with search and warp in one pass (me_estimate_warp): the
+    search workgroups write their blocks' warped cells as soon as the blocks'
+    vectors are known.  frames/s over the timed steps and the fused kernel's
+    event-timed duration per pair."""
+    import numpy as np
+    import torch
+
+    params = me.make_params(B, R)
+    npairs = len(frames) - 1
+
+    def step(ev=None):
+        for t in range(npairs):
+            if ev is not None:
+                ev[0][t].record()
+            me.estimate_warp(frames[t], frames[t + 1], z, mv=mvs[t], sad=sads[t], out=outs[t & 1], params=params,
+                             ctx=ctx)
+            if ev is not None:
+                ev[1][t].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[[torch.cuda.Event(enable_timing=True) for _ in range(npairs)] for _ in range(2)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = float(np.mean([evs[k][0][t].elapsed_time(evs[k][1][t]) for k in range(args.steps) for t in range(npairs)]))
+    return {"value": round(npairs * args.steps / wall, 2), "unit": "frames/s", "fused_ms_per_pair": round(ms, 5),
+            "ms_per_step": round(wall * 1e3 / args.steps, 4)}
+
+
 def paper_shapes_leg(me, ctx, args):
     """Like-for-like context for the paper's runtimes (Sec. 4.2): one frame pair
     at the CamVid (720x960) and Cityscapes (1024x2048) Bayer shapes, synthetic
@@ -601,6 +635,7 @@ def main():
         "step_roofline_frac": round((ops / (PEAK_SAD_TOPS * 1e12) + warp_bytes / (PEAK_HBM_GBS * 1e9))
                                     / (wall / (npairs * args.steps)), 4),
     }
+    res["fused_search_warp"] = fused_leg(me, ctx, frames, z, mvs, sads, outs, B, R, H, W, args)
     if not args.no_proposal:
         res["proposal"] = proposal_leg(me, ctx, frames, mvs, z, outs, B, R, H, W, args)
     if not args.no_pyramid:

@@ -180,6 +180,21 @@ me_status me_warp_features(me_ctx ctx, const void* z_ref, void* z_out, int32_t d
                            void* stream);
 
 /*
+ * me_estimate_warp -- me_estimate (exhaustive, step 1) and me_warp_features in
+ * one pass: each workgroup of the search, once its blocks' vectors are known,
+ * writes those blocks' cells of z_out = Warp(z_ref, MV) (paper Sec. 3.3), so
+ * the warp's memory traffic overlaps the search's integer work and needs no
+ * second launch.  Arguments as in me_estimate (mv, sad written) and
+ * me_warp_features (z_ref, z_out, dtype, C, Hf, Wf; the map tiles the packed
+ * frame with square cells that divide the block; z_out may not overlap z_ref).
+ * Results are bit-identical to me_estimate followed by me_warp_features.
+ * Radii served by the small-radius kernel (<= 4) run the two kernels in turn.
+ */
+me_status me_estimate_warp(me_ctx ctx, const me_frame* ref, const me_frame* cur, const me_params* params, int16_t* mv,
+                           int32_t* sad, const void* z_ref, void* z_out, int32_t dtype, int32_t C, int32_t Hf,
+                           int32_t Wf, void* stream);
+
+/*
  * me_compose_vectors -- chain block vectors over a group of pictures (paper
  * Sec. 4.1 GOP test protocol; Sec. 4.4 compares references).  mv_step maps the
  * blocks of frame t to frame t-1, mv_acc_in the blocks of frame t-1 to the key

@@ -395,35 +395,92 @@ me_status me_pyramid(me_ctx ctx, const me_frame* ref, const me_frame* cur, const
     return ME_OK;
 }
 
+namespace {
+
+// Validation shared by the warp entry points; *s_out receives the cell size.
+me_status check_warp(const char* who, const void* z_ref, void* z_out, int32_t dtype, int32_t C, int32_t Hf, int32_t Wf,
+                     int32_t block, int32_t frame_h, int32_t frame_w, int* s_out)
+{
+    if (!z_ref || !z_out) return fail(ME_E_INVAL, "%s: null feature pointer", who);
+    if (dtype != ME_F32 && dtype != ME_BF16) return fail(ME_E_INVAL, "%s: unknown dtype %d", who, dtype);
+    if (C < 1 || Hf < 1 || Wf < 1) return fail(ME_E_INVAL, "%s: empty feature map", who);
+    if ((long long)C * Hf * Wf > (1LL << 40)) return fail(ME_E_UNSUPPORTED, "%s: map too large", who);
+    if ((long long)Hf * Wf > 0x7fffffffLL) return fail(ME_E_UNSUPPORTED, "%s: plane too large", who);
+    if (!block_ok(block)) return fail(ME_E_UNSUPPORTED, "%s: block %d not in {8,16,32,64}", who, block);
+    if (frame_h < 2 || frame_w < 2 || (frame_h & 1) || (frame_w & 1))
+        return fail(ME_E_INVAL, "%s: frame size must be even and >= 2", who);
+    const int Hp = frame_h / 2, Wp = frame_w / 2;
+    if (Hp % Hf || Wp % Wf || Hp / Hf != Wp / Wf)
+        return fail(ME_E_UNSUPPORTED, "%s: %dx%d map does not tile the %dx%d packed frame with square cells", who, Hf,
+                    Wf, Hp, Wp);
+    const int s = Hp / Hf;
+    if (block % s) return fail(ME_E_UNSUPPORTED, "%s: cell size %d does not divide block %d", who, s, block);
+    const size_t esz = dtype == ME_F32 ? 4 : 2;
+    const char* a0 = static_cast<const char*>(z_ref);
+    const char* b0 = static_cast<const char*>(z_out);
+    const size_t bytes = (size_t)C * Hf * Wf * esz;
+    if (a0 < b0 + bytes && b0 < a0 + bytes) return fail(ME_E_INVAL, "%s: z_out overlaps z_ref", who);
+    *s_out = s;
+    return ME_OK;
+}
+
+}  // namespace
+
 me_status me_warp_features(me_ctx ctx, const void* z_ref, void* z_out, int32_t dtype, int32_t C, int32_t Hf,
                            int32_t Wf, const int16_t* mv, int32_t block, int32_t frame_h, int32_t frame_w,
                            void* stream)
 {
     (void)ctx;
-    if (!z_ref || !z_out || !mv) return fail(ME_E_INVAL, "me_warp_features: null pointer");
-    if (dtype != ME_F32 && dtype != ME_BF16) return fail(ME_E_INVAL, "me_warp_features: unknown dtype %d", dtype);
-    if (C < 1 || Hf < 1 || Wf < 1) return fail(ME_E_INVAL, "me_warp_features: empty feature map");
-    if ((long long)C * Hf * Wf > (1LL << 40)) return fail(ME_E_UNSUPPORTED, "me_warp_features: map too large");
-    if ((long long)Hf * Wf > 0x7fffffffLL) return fail(ME_E_UNSUPPORTED, "me_warp_features: plane too large");
-    if (!block_ok(block)) return fail(ME_E_UNSUPPORTED, "me_warp_features: block %d not in {8,16,32,64}", block);
-    if (frame_h < 2 || frame_w < 2 || (frame_h & 1) || (frame_w & 1))
-        return fail(ME_E_INVAL, "me_warp_features: frame size must be even and >= 2");
-    const int Hp = frame_h / 2, Wp = frame_w / 2;
-    if (Hp % Hf || Wp % Wf || Hp / Hf != Wp / Wf)
-        return fail(ME_E_UNSUPPORTED, "me_warp_features: %dx%d map does not tile the %dx%d packed frame with square cells",
-                    Hf, Wf, Hp, Wp);
-    const int s = Hp / Hf;
-    if (block % s) return fail(ME_E_UNSUPPORTED, "me_warp_features: cell size %d does not divide block %d", s, block);
-    const size_t esz = dtype == ME_F32 ? 4 : 2;
-    const char* a0 = static_cast<const char*>(z_ref);
-    const char* b0 = static_cast<const char*>(z_out);
-    const size_t bytes = (size_t)C * Hf * Wf * esz;
-    if (a0 < b0 + bytes && b0 < a0 + bytes) return fail(ME_E_INVAL, "me_warp_features: z_out overlaps z_ref");
+    if (!mv) return fail(ME_E_INVAL, "me_warp_features: null pointer");
+    int s = 0;
+    me_status st = check_warp("me_warp_features", z_ref, z_out, dtype, C, Hf, Wf, block, frame_h, frame_w, &s);
+    if (st != ME_OK) return st;
     if ((reinterpret_cast<uintptr_t>(mv) & 3u)) return fail(ME_E_INVAL, "me_warp_features: mv must be 4-byte aligned");
-    const int bw = (Wp + block - 1) / block;
+    const int bw = (frame_w / 2 + block - 1) / block;
     hipError_t e = launch_warp(z_ref, z_out, dtype == ME_BF16, C, Hf, Wf, mv, bw, block / s, s,
                                reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "me_warp_features: launch");
+    return ME_OK;
+}
+
+me_status me_estimate_warp(me_ctx ctx, const me_frame* ref, const me_frame* cur, const me_params* params, int16_t* mv,
+                           int32_t* sad, const void* z_ref, void* z_out, int32_t dtype, int32_t C, int32_t Hf,
+                           int32_t Wf, void* stream)
+{
+    me_status st = check_pair(ref, cur);
+    if (st != ME_OK) return st;
+    if (!params) return fail(ME_E_INVAL, "me_estimate_warp: null params");
+    if (!mv || !sad) return fail(ME_E_INVAL, "me_estimate_warp: null mv or sad");
+    const me_params& p = *params;
+    if (!block_ok(p.block)) return fail(ME_E_UNSUPPORTED, "me_estimate_warp: block %d not in {8,16,32,64}", p.block);
+    if (p.radius < 0 || p.radius > 64) return fail(ME_E_INVAL, "me_estimate_warp: radius %d not in [0,64]", p.radius);
+    if (p.step != 1 || p.mode != ME_MODE_EXHAUSTIVE)
+        return fail(ME_E_UNSUPPORTED, "me_estimate_warp: exhaustive mode with step 1 only");
+    if ((reinterpret_cast<uintptr_t>(mv) & 3u)) return fail(ME_E_INVAL, "me_estimate_warp: mv must be 4-byte aligned");
+    int s = 0;
+    st = check_warp("me_estimate_warp", z_ref, z_out, dtype, C, Hf, Wf, p.block, cur->height, cur->width, &s);
+    if (st != ME_OK) return st;
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    SearchArgs a = make_args(ref, cur, p.block, p.radius, p.radius, nullptr, mv, sad);
+    const TileCfg cfg = tiles_for(ctx, p.block, p.radius, a.Hp, a.Wp);
+    hipError_t e;
+    if (small_search(p.block, p.radius)) {
+        // the small-radius kernel has no warp epilogue: search, then the warp kernel
+        e = launch_sad_search(a, cfg, a.bh * a.bw, hs);
+        if (e == hipSuccess)
+            e = launch_warp(z_ref, z_out, dtype == ME_BF16, C, Hf, Wf, mv, a.bw, p.block / s, s, hs);
+    } else {
+        a.wz = z_ref;
+        a.wout = z_out;
+        a.wC = C;
+        a.wHf = Hf;
+        a.wWf = Wf;
+        a.ws = s;
+        a.wbf16 = dtype == ME_BF16;
+        a.winv_s = 1.0f / (float)s;
+        e = launch_sad_search(a, cfg, a.bh * a.bw, hs);
+    }
+    if (e != hipSuccess) return hip_fail(e, "me_estimate_warp: launch");
     return ME_OK;
 }
 

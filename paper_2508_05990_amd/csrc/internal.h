@@ -51,6 +51,14 @@ struct SearchArgs {
     // network output [3][bh][bw], clamp(rint(8 o), -limit, limit), instead of
     // `pred`; null otherwise
     const float* net;
+    // fused warp (tiled and generic kernels, single pair): once a block's
+    // vector is known, its workgroup also writes the block's cells of
+    // wout = Warp(wz, MV) ([wC][wHf][wWf], cell size ws packed pixels, float32
+    // or bfloat16).  wz null: no warp.
+    const void* wz;
+    void* wout;
+    int32_t wC, wHf, wWf, ws, wbf16;
+    float winv_s;
 };
 
 

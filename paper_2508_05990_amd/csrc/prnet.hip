@@ -29,7 +29,6 @@ namespace me {
 namespace {
 
 constexpr int kPx = 64;       // pixels per GEMM workgroup
-constexpr int kNG = 8;        // output-channel tiles per accumulation pass
 constexpr int kTPW = 16;      // weight-gradient tiles per wave
 constexpr int kLdp = kPx + 4; // LDS row length (bfloat16) of channel-major tiles (8-byte aligned rows)
 

@@ -16,7 +16,9 @@
 //
 // Blocks of full width take the register-tiled kernel; blocks cut by the
 // right frame edge (width < B) take a plain one-candidate-per-lane kernel.
+#include "bf16.h"
 #include "internal.h"
+#include "warp_cell.h"
 
 namespace me {
 namespace {
@@ -342,6 +344,86 @@ __device__ __forceinline__ void block_band(const SearchArgs& a, const BlockGeo& 
 
 // Tiled search of the full-width blocks [first_blk, first_blk + nblk) of one
 // block row by the whole workgroup (4 waves per block; all threads call it).
+// Fused warp: the cells of block blk of wout = Warp(wz, MV) for the block's
+// final key (the vector write_result stores), threads t = 0..nt-1 of the
+// block.  A thread keeps one cell (taps and weights computed once) and walks
+// channels t / ncell, + nt / ncell, ..., loading four channels' taps before
+// using them, as the warp kernel does; same arithmetic, so the same bits.
+template <bool BF16>
+__device__ void warp_block_t(const SearchArgs& a, int blk, uint64_t best, int t, int nt)
+{
+    const int dx = best == ~0ull ? 0 : (int)(best & 0xffu) - 128;
+    const int dy = best == ~0ull ? 0 : (int)((best >> 8) & 0xffu) - 128;
+    const int cells = a.block / a.ws;
+    const int bi = blk / a.bw, bj = blk - bi * a.bw;
+    const int i0 = bi * cells, j0 = bj * cells;
+    const int nci = min(cells, a.wHf - i0), ncj = min(cells, a.wWf - j0);
+    if (nci <= 0 || ncj <= 0) return;
+    const int ncell = nci * ncj;
+    const int lanes_per_ch = nt / ncell;                  // threads sharing a cell, on different channels
+    if (lanes_per_ch == 0) {
+        // more cells than threads (a block of 64 with cells of 1 or 2): one item at a time
+        const size_t plane = (size_t)a.wHf * a.wWf;
+        for (int item = t; item < a.wC * ncell; item += nt) {
+            const int c = item / ncell, k = item - c * ncell;
+            const int i = i0 + k / ncj, j = j0 + k % ncj;
+            const WarpTaps tp = warp_taps(i, j, dx, dy, a.ws, a.winv_s, a.wHf, a.wWf);
+            const size_t base = (size_t)c * plane, o = base + (size_t)i * a.wWf + j;
+            if (BF16) {
+                const uint16_t* p = static_cast<const uint16_t*>(a.wz) + base;
+                static_cast<uint16_t*>(a.wout)[o] =
+                    f2bf(warp_mix(tp, bf2f(p[tp.o00]), bf2f(p[tp.o01]), bf2f(p[tp.o10]), bf2f(p[tp.o11])));
+            } else {
+                const float* p = static_cast<const float*>(a.wz) + base;
+                static_cast<float*>(a.wout)[o] = warp_mix(tp, p[tp.o00], p[tp.o01], p[tp.o10], p[tp.o11]);
+            }
+        }
+        return;
+    }
+    const int k = t % ncell, c0 = t / ncell;
+    if (c0 >= lanes_per_ch) return;
+    const int i = i0 + k / ncj, j = j0 + k % ncj;
+    const WarpTaps tp = warp_taps(i, j, dx, dy, a.ws, a.winv_s, a.wHf, a.wWf);
+    const size_t plane = (size_t)a.wHf * a.wWf, cell = (size_t)i * a.wWf + j;
+    for (int cb = c0; cb < a.wC; cb += 4 * lanes_per_ch) {
+        float v[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            int c = cb + u * lanes_per_ch;
+            c = c < a.wC ? c : a.wC - 1;
+            const size_t base = (size_t)c * plane;
+            if (BF16) {
+                const uint16_t* p = static_cast<const uint16_t*>(a.wz) + base;
+                v[u][0] = bf2f(p[tp.o00]);
+                v[u][1] = bf2f(p[tp.o01]);
+                v[u][2] = bf2f(p[tp.o10]);
+                v[u][3] = bf2f(p[tp.o11]);
+            } else {
+                const float* p = static_cast<const float*>(a.wz) + base;
+                v[u][0] = p[tp.o00];
+                v[u][1] = p[tp.o01];
+                v[u][2] = p[tp.o10];
+                v[u][3] = p[tp.o11];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = cb + u * lanes_per_ch;
+            if (c >= a.wC) break;
+            const float r = warp_mix(tp, v[u][0], v[u][1], v[u][2], v[u][3]);
+            const size_t o = (size_t)c * plane + cell;
+            if (BF16) static_cast<uint16_t*>(a.wout)[o] = f2bf(r);
+            else static_cast<float*>(a.wout)[o] = r;
+        }
+    }
+}
+
+__device__ __forceinline__ void warp_block(const SearchArgs& a, int blk, uint64_t best, int t, int nt)
+{
+    if (a.wbf16) warp_block_t<true>(a, blk, best, t, nt);
+    else warp_block_t<false>(a, blk, best, t, nt);
+}
+
 template <int CW, int NCH, int KX, int KY>
 __device__ __forceinline__ void run_tiled(const SearchArgs& a, int first_blk, int nblk, uint32_t* lds, uint64_t* red)
 {
@@ -383,6 +465,12 @@ __device__ __forceinline__ void run_tiled(const SearchArgs& a, int first_blk, in
         for (int k = 1; k < kWavesPerBlock; ++k) b = red[wave + k] < b ? red[wave + k] : b;
         write_result(a, g.blk, b);
     }
+    if (a.wz && has_block) {
+        const int w0 = mine * kWavesPerBlock;
+        uint64_t b = red[w0];
+        for (int k = 1; k < kWavesPerBlock; ++k) b = red[w0 + k] < b ? red[w0 + k] : b;
+        warp_block(a, g.blk, b, wib * 64 + lane, kWavesPerBlock * 64);
+    }
 }
 
 // One block of any width, one candidate per lane (a.band_ty candidate rows
@@ -422,6 +510,11 @@ __device__ __forceinline__ void run_generic(const SearchArgs& a, int blk, uint32
         uint64_t b = red[0];
         for (int k = 1; k < nw; ++k) b = red[k] < b ? red[k] : b;
         write_result(a, blk, b);
+    }
+    if (a.wz) {
+        uint64_t b = red[0];
+        for (int k = 1; k < nw; ++k) b = red[k] < b ? red[k] : b;
+        warp_block(a, blk, b, tid, nt);
     }
 }
 

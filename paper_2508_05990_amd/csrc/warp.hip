@@ -7,27 +7,12 @@
 // bilinear weights are computed once per thread and reused for every channel
 // of its chunk; consecutive lanes take consecutive cells of a row, so loads
 // and stores of a channel plane are contiguous across the wave.
+#include "bf16.h"
 #include "internal.h"
+#include "warp_cell.h"
 
 namespace me {
 namespace {
-
-__device__ __forceinline__ float bf16_to_f32(uint16_t v) { return __uint_as_float((uint32_t)v << 16); }
-
-// Round to nearest, ties to even; NaN stays a quiet NaN.
-__device__ __forceinline__ uint16_t f32_to_bf16(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-
-__device__ __forceinline__ int floor_div(int a, int b)
-{
-    const int q = a / b;
-    return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
-}
 
 // One cell per lane (consecutive lanes, consecutive cells: every load and
 // store instruction of a wave covers a contiguous stretch of a plane) and a
@@ -54,15 +39,8 @@ __global__ __launch_bounds__(256) void warp_kernel(const void* __restrict__ zin,
     const int b = (i / cells) * bw + (j / cells);
     const int32_t vec = reinterpret_cast<const int32_t*>(mv)[b];   // (dx, dy) as two int16
     const int dx = (int16_t)(vec & 0xffff), dy = (int16_t)((uint32_t)vec >> 16);
-    const int ny = i * s + dy, nx = j * s + dx;
-    const int y0 = floor_div(ny, s), x0 = floor_div(nx, s);
-    const float wy = (float)(ny - y0 * s) * inv_s;
-    const float wx = (float)(nx - x0 * s) * inv_s;
-    const int ya = min(max(y0, 0), Hf - 1), yb = min(max(y0 + 1, 0), Hf - 1);
-    const int xa = min(max(x0, 0), Wf - 1), xb = min(max(x0 + 1, 0), Wf - 1);
-    const float w00 = (1.f - wy) * (1.f - wx), w01 = (1.f - wy) * wx;
-    const float w10 = wy * (1.f - wx), w11 = wy * wx;
-    const int o00 = ya * Wf + xa, o01 = ya * Wf + xb, o10 = yb * Wf + xa, o11 = yb * Wf + xb;
+    const WarpTaps tp = warp_taps(i, j, dx, dy, s, inv_s, Hf, Wf);
+    const int o00 = tp.o00, o01 = tp.o01, o10 = tp.o10, o11 = tp.o11;
 
     const size_t plane = (size_t)ncell;
     for (int cb = c0; cb < c1; cb += 4) {
@@ -73,10 +51,10 @@ __global__ __launch_bounds__(256) void warp_kernel(const void* __restrict__ zin,
             const size_t base = (size_t)c * plane;
             if (BF16) {
                 const uint16_t* p = reinterpret_cast<const uint16_t*>(zin) + base;
-                v[u][0] = bf16_to_f32(p[o00]);
-                v[u][1] = bf16_to_f32(p[o01]);
-                v[u][2] = bf16_to_f32(p[o10]);
-                v[u][3] = bf16_to_f32(p[o11]);
+                v[u][0] = bf2f(p[o00]);
+                v[u][1] = bf2f(p[o01]);
+                v[u][2] = bf2f(p[o10]);
+                v[u][3] = bf2f(p[o11]);
             } else {
                 const float* p = reinterpret_cast<const float*>(zin) + base;
                 v[u][0] = p[o00];
@@ -88,13 +66,10 @@ __global__ __launch_bounds__(256) void warp_kernel(const void* __restrict__ zin,
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             if (cb + u >= c1) break;
-            float acc = w00 * v[u][0];
-            acc = fmaf(w01, v[u][1], acc);
-            acc = fmaf(w10, v[u][2], acc);
-            acc = fmaf(w11, v[u][3], acc);
+            const float acc = warp_mix(tp, v[u][0], v[u][1], v[u][2], v[u][3]);
             const size_t o = (size_t)(cb + u) * plane + cell;
             if (BF16)
-                reinterpret_cast<uint16_t*>(zout)[o] = f32_to_bf16(acc);
+                reinterpret_cast<uint16_t*>(zout)[o] = f2bf(acc);
             else
                 reinterpret_cast<float*>(zout)[o] = acc;
         }

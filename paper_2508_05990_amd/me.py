@@ -68,6 +68,8 @@ class MePyramidCfg(ctypes.Structure):
 
 
 _me_compose_vectors = _sig("me_compose_vectors", [_P, _P, _P, _I32, _I32, _I32, _P])
+_me_estimate_warp = _sig("me_estimate_warp", [_P, ctypes.POINTER(MeFrame), ctypes.POINTER(MeFrame),
+                                              ctypes.POINTER(MeParams), _P, _P, _P, _P, _I32, _I32, _I32, _I32, _P])
 _me_default_pyramid = _sig("me_default_pyramid", [], MePyramidCfg)
 _me_pyramid = _sig("me_pyramid", [_P, ctypes.POINTER(MeFrame), ctypes.POINTER(MeFrame), ctypes.POINTER(MePyramidCfg),
                                   _P, _P, _P])
@@ -125,7 +127,7 @@ EXPORTS = ["me_default_params", "me_ctx_create", "me_ctx_destroy", "me_estimate"
            "me_cnn_set_params", "me_cnn_get_params", "me_cnn_pool", "me_cnn_forward", "me_cnn_train_step",
            "me_cnn_state_bytes", "me_cnn_save_state", "me_cnn_load_state", "me_cnn_layer_forward",
            "me_cnn_layer_backward", "me_cnn_loss", "me_cnn_adamw", "me_autotune", "me_pyramid",
-           "me_default_pyramid", "me_compose_vectors", "me_prnet_num_params", "me_prnet_create", "me_prnet_destroy",
+           "me_default_pyramid", "me_compose_vectors", "me_estimate_warp", "me_prnet_num_params", "me_prnet_create", "me_prnet_destroy",
            "me_prnet_set_params", "me_prnet_get_params", "me_prnet_forward", "me_prnet_train_step",
            "me_prnet_dw_forward", "me_prnet_dw_backward", "me_prnet_pw_forward", "me_prnet_pw_backward",
            "me_prnet_loss"]
@@ -235,6 +237,25 @@ def stage_search(ref, cur, block, radius, pred=None, limit=None, mv=None, sad=No
                             None if pred is None else pred.data_ptr(), limit, mv.data_ptr(), sad.data_ptr(),
                             _stream_handle(stream)))
     return mv, sad
+
+
+def estimate_warp(ref, cur, z_ref, block=16, radius=32, mv=None, sad=None, out=None, params=None, ctx=None,
+                  stream=None):
+    """Full search and warp in one pass (me_estimate_warp): returns (mv, sad, z_out)."""
+    fr, fc = frame_of(ref), frame_of(cur)
+    p = params if params is not None else make_params(block, radius)
+    bh, bw = block_grid(ref.shape[0], ref.shape[1], p.block)
+    if mv is None:
+        mv = torch.empty((bh, bw, 2), dtype=torch.int16, device=ref.device)
+    if sad is None:
+        sad = torch.empty((bh, bw), dtype=torch.int32, device=ref.device)
+    if out is None:
+        out = torch.empty_like(z_ref)
+    C, Hf, Wf = z_ref.shape
+    dt = ME_BF16 if z_ref.dtype == torch.bfloat16 else ME_F32
+    _check(_me_estimate_warp(_ctx_handle(ctx), ctypes.byref(fr), ctypes.byref(fc), ctypes.byref(p), mv.data_ptr(),
+                             sad.data_ptr(), z_ref.data_ptr(), out.data_ptr(), dt, C, Hf, Wf, _stream_handle(stream)))
+    return mv, sad, out
 
 
 def compose_vectors(mv_step, mv_acc, block, frame_h, frame_w, out=None, stream=None):

@@ -230,3 +230,20 @@ def test_prnet_init_params_layout(me):
     for (W, b), (kind, ci, co, _, act) in zip(P.unpack(p, cfg), P.layer_specs(cfg)):
         assert np.all(b == (np.float32(0.1) if act else 0.0))
         assert W.shape == ((co, 9) if kind == "dw" else (co, ci))
+
+
+def test_estimate_warp_validation(me):
+    p = me.default_params()
+    fr = _frame(me)
+    args = lambda prm, z=FAKE, o=FAKE + 0x100000, C=4, Hf=8, Wf=8, dt=0: (
+        None, ctypes.byref(fr), ctypes.byref(fr), ctypes.byref(prm), FAKE, FAKE, z, o, dt, C, Hf, Wf, None)
+    assert me._me_estimate_warp(*args(p, z=None)) == me.ME_E_INVAL
+    assert me._me_estimate_warp(*args(p, dt=7)) == me.ME_E_INVAL
+    assert me._me_estimate_warp(*args(p, Hf=7)) == me.ME_E_UNSUPPORTED       # cells do not tile the frame
+    assert me._me_estimate_warp(*args(p, o=FAKE + 16)) == me.ME_E_INVAL      # output overlaps the map
+    q = me.default_params()
+    q.mode = me.ME_MODE_PROPOSAL
+    assert me._me_estimate_warp(*args(q)) == me.ME_E_UNSUPPORTED
+    q = me.default_params()
+    q.block = 12
+    assert me._me_estimate_warp(*args(q)) == me.ME_E_UNSUPPORTED
