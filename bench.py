@@ -28,7 +28,7 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the search kernel from rocprofv3 FETCH_SIZE/WRITE_SIZE
 # (scaled by a plain-copy calibration: FETCH x2, WRITE x1), valid for the
 # kernel source with this SHA-256 prefix only; reported as null otherwise.
-SAD_TRAFFIC = {"source_sha256_16": "50740b2ccddf60ab", "bytes": 7934.06 * 1024 * 2 + 16.13 * 1024}
+SAD_TRAFFIC = {"source_sha256_16": "0145aa2c8a4fc165", "bytes": 7942.55 * 1024 * 2 + 16.13 * 1024}
 SAD_SOURCE = os.path.join(ROOT, "paper_2508_05990_amd", "csrc", "sad_search.hip")
 
 
@@ -532,6 +532,7 @@ def main():
     ap.add_argument("--no-gop", action="store_true", help="skip the group-of-pictures propagation measurement")
     ap.add_argument("--no-prnet", action="store_true", help="skip the residual-network measurement")
     ap.add_argument("--no-paper-shapes", action="store_true", help="skip the paper-shape context measurement")
+    ap.add_argument("--no-fused", action="store_true", help="skip the one-pass search + warp measurement")
     ap.add_argument("--uhd-frames", type=int, default=16, help="frames of the 4K sequence (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes (reference for HBM byte counters)")
@@ -635,7 +636,8 @@ def main():
         "step_roofline_frac": round((ops / (PEAK_SAD_TOPS * 1e12) + warp_bytes / (PEAK_HBM_GBS * 1e9))
                                     / (wall / (npairs * args.steps)), 4),
     }
-    res["fused_search_warp"] = fused_leg(me, ctx, frames, z, mvs, sads, outs, B, R, H, W, args)
+    if not args.no_fused:
+        res["fused_search_warp"] = fused_leg(me, ctx, frames, z, mvs, sads, outs, B, R, H, W, args)
     if not args.no_proposal:
         res["proposal"] = proposal_leg(me, ctx, frames, mvs, z, outs, B, R, H, W, args)
     if not args.no_pyramid:
