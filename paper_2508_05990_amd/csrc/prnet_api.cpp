@@ -392,7 +392,9 @@ hipError_t pw_dgrad(me_prnet net, const Layer& l, PwTensor dy, int HW, int P, co
     return launch_pw(a, st);
 }
 
-hipError_t run_backward(me_prnet net, const void* zp, hipStream_t st)
+// The projection's weight gradient reads z_pred as the forward pass left it
+// (channels-last bfloat16 in net->zl).
+hipError_t run_backward(me_prnet net, hipStream_t st)
 {
     const me_prnet_cfg& c = net->cfg;
     const std::vector<Layer>& L = net->L;
@@ -424,7 +426,6 @@ hipError_t run_backward(me_prnet net, const void* zp, hipStream_t st)
     if (e != hipSuccess) return e;
     // projection: input [z_pred, e4]; its gradient reaches e4 only
     const PwTensor dp = nhwc(net->dh[cur], c.c_hid);
-    (void)zp;                                     // the forward pass left z_pred channels-last in net->zl
     e = pw_grad(net, L[4], nhwc(net->zl, c.c_feat), nhwc(net->e4, c.c_enc), dp, HW2, P2, st);
     if (e == hipSuccess) e = pw_dgrad(net, L[4], dp, HW2, P2, nullptr, net->e4, net->gA, st);              // de4
     if (e == hipSuccess) e = pw_grad(net, L[3], nhwc(net->e3, c.c_enc), none(), nhwc(net->gA, c.c_enc), HW2, P2, st);
@@ -560,7 +561,7 @@ me_status me_prnet_train_step(me_prnet net, const me_frame* cur, int32_t n, int6
     if (e == hipSuccess)
         e = launch_prloss(net->r, z_pred, z_target, n, net->cfg.c_feat, HW2, tau, net->nbad, net->maxbits, net->flags,
                           net->dr, net->lpart, loss, st);
-    if (e == hipSuccess) e = run_backward(net, z_pred, st);
+    if (e == hipSuccess) e = run_backward(net, st);
     if (e == hipSuccess && grads) e = hipMemcpyAsync(grads, net->grads, net->np * 4, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess && update) {
         net->step += 1;
