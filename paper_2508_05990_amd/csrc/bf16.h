@@ -15,14 +15,17 @@ typedef float v4f32 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float bf2f(uint16_t v) { return __uint_as_float((uint32_t)v << 16); }
 
-// Round to nearest even; NaN stays NaN.
-__device__ __forceinline__ uint16_t f2bf(float f)
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+// Round to nearest even (gfx950's v_cvt_pk_bf16_f32: two values per
+// instruction); NaN stays NaN.
+__device__ __forceinline__ uint32_t pack2(float a, float b)
 {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    const bf16x2_t v = {(__bf16)a, (__bf16)b};
+    return __builtin_bit_cast(uint32_t, v);
 }
+
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
 __device__ __forceinline__ v4i16 as_v4(uint2 u)
 {
@@ -34,13 +37,7 @@ __device__ __forceinline__ v4i16 as_v4(uint2 u)
     return r;
 }
 
-__device__ __forceinline__ uint2 pack4(float a, float b, float c, float d)
-{
-    uint2 r;
-    r.x = (uint32_t)f2bf(a) | (uint32_t)f2bf(b) << 16;
-    r.y = (uint32_t)f2bf(c) | (uint32_t)f2bf(d) << 16;
-    return r;
-}
+__device__ __forceinline__ uint2 pack4(float a, float b, float c, float d) { return make_uint2(pack2(a, b), pack2(c, d)); }
 
 __device__ __forceinline__ float4 unpack4(uint2 u)
 {

@@ -650,13 +650,14 @@ __global__ __launch_bounds__(256) void ir_block_kernel(IrArgs a)
     uint16_t* hl = lds;                                   // [112][CH + 8]   h over tile + halo
     uint16_t* ul = hl + kIrRows * ldh;                     // [112][72]       u, one chunk
     uint16_t* vl = ul + kIrRows * kIrLd;                   // [64][72]        v, one chunk
-    float* wl = reinterpret_cast<float*>(vl + kIrT * kIrT * kIrLd);   // [64][10] depthwise weights + bias, [64] expansion bias
+    float* wl = reinterpret_cast<float*>(vl + kIrT * kIrT * kIrLd);   // [X][10] depthwise weights + bias, [X] expansion bias
     const int tiles_x = (a.Wf + kIrT - 1) / kIrT, tiles_y = (a.Hf + kIrT - 1) / kIrT;
     const int img = blockIdx.x / (tiles_x * tiles_y), tr = blockIdx.x - img * tiles_x * tiles_y;
     const int y0 = (tr / tiles_x) * kIrT, x0 = (tr % tiles_x) * kIrT;
     constexpr int c4n = CH >> 2;
     const uint2* hin = reinterpret_cast<const uint2*>(a.h_in) + (size_t)img * a.Hf * a.Wf * c4n;
 
+    // every global read but the packed weights happens here, once
     for (int e = threadIdx.x; e < kIrRows * c4n; e += blockDim.x) {
         const int hp = e / c4n, c4 = e - hp * c4n;
         uint2 v = make_uint2(0u, 0u);
@@ -666,45 +667,53 @@ __global__ __launch_bounds__(256) void ir_block_kernel(IrArgs a)
         }
         *reinterpret_cast<uint2*>(hl + hp * ldh + 4 * c4) = v;
     }
+    for (int e = threadIdx.x; e < X * 11; e += blockDim.x) {
+        const int ch = e / 11, t = e - ch * 11;
+        wl[t < 10 ? ch * 10 + t : X * 10 + ch] = t < 9 ? a.wd[ch * 9 + t] : (t == 9 ? a.bd[ch] : a.be[ch]);
+    }
 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, n = lane & 15;
     const uint2* we = reinterpret_cast<const uint2*>(a.we);
     const uint2* wc = reinterpret_cast<const uint2*>(a.wc);
     constexpr int KSe = CH >> 4, MTc = CH >> 4, MPW = (MTc + 3) / 4;   // compression row tiles per wave
-    const int KSc = X >> 4;
+    const int KSc = X >> 4, nq = X / kIrChunk;
     // Wave w owns expansion row tile w of every chunk (16 of its 64 channels)
     // and compression row tiles w, w + 4, ...: it loads only those weights and
-    // reuses them across all column (pixel) tiles.
+    // reuses them across all column (pixel) tiles; the next chunk's weights are
+    // loaded while the current chunk is computed.
     v4f32 acc2[MPW][4];
 #pragma unroll
     for (int j = 0; j < MPW; ++j)
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) acc2[j][nt] = (v4f32){0.f, 0.f, 0.f, 0.f};
     const int c4 = threadIdx.x & 15;                       // channel group of this thread in the depthwise step
+    v4i16 wa[KSe], wb[MPW][4];
+#pragma unroll
+    for (int ks = 0; ks < KSe; ++ks) wa[ks] = as_v4(we[((size_t)w * KSe + ks) * 64 + lane]);
+#pragma unroll
+    for (int j = 0; j < MPW; ++j)
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+            wb[j][ks] = w + 4 * j < MTc ? as_v4(wc[((size_t)(w + 4 * j) * KSc + ks) * 64 + lane]) : as_v4(make_uint2(0u, 0u));
+    __syncthreads();
 
 #pragma unroll 1
-    for (int q = 0; q < X / kIrChunk; ++q) {
-        v4i16 wa[KSe];
+    for (int q = 0; q < nq; ++q) {
+        v4i16 wa_n[KSe], wb_n[MPW][4];
+        const int qn = q + 1 < nq ? q + 1 : q;
 #pragma unroll
-        for (int ks = 0; ks < KSe; ++ks) wa[ks] = as_v4(we[((size_t)(4 * q + w) * KSe + ks) * 64 + lane]);
-        v4i16 wb[MPW][4];
+        for (int ks = 0; ks < KSe; ++ks) wa_n[ks] = as_v4(we[((size_t)(4 * qn + w) * KSe + ks) * 64 + lane]);
 #pragma unroll
         for (int j = 0; j < MPW; ++j)
 #pragma unroll
             for (int ks = 0; ks < 4; ++ks)
-                wb[j][ks] = w + 4 * j < MTc ? as_v4(wc[((size_t)(w + 4 * j) * KSc + 4 * q + ks) * 64 + lane])
-                                            : as_v4(make_uint2(0u, 0u));
-        __syncthreads();                                   // h staged / previous chunk's u, v and weights read
-        for (int e = threadIdx.x; e < kIrChunk * 11; e += blockDim.x) {
-            const int cc = e / 11, t = e - cc * 11;
-            const int ch = q * kIrChunk + cc;
-            wl[t < 10 ? cc * 10 + t : kIrChunk * 10 + cc] = t < 9 ? a.wd[ch * 9 + t] : (t == 9 ? a.bd[ch] : a.be[ch]);
-        }
-        __syncthreads();
-        // expansion: channels 64 q + 16 w .. + 15 for the 112 halo rows
+                wb_n[j][ks] = w + 4 * j < MTc ? as_v4(wc[((size_t)(w + 4 * j) * KSc + 4 * qn + ks) * 64 + lane])
+                                              : as_v4(make_uint2(0u, 0u));
+        // expansion: channels 64 q + 16 w .. + 15 for the 112 halo rows (the previous
+        // chunk's depthwise reads of u finished before its compression barrier)
         const int oe = 16 * w + 4 * g;
-        const float be0 = wl[kIrChunk * 10 + oe], be1 = wl[kIrChunk * 10 + oe + 1], be2 = wl[kIrChunk * 10 + oe + 2],
-                    be3 = wl[kIrChunk * 10 + oe + 3];
+        const float* bexp = wl + X * 10 + q * kIrChunk + oe;
+        const float be0 = bexp[0], be1 = bexp[1], be2 = bexp[2], be3 = bexp[3];
 #pragma unroll 1
         for (int nt = 0; nt < kIrRows / 16; ++nt) {
             const int hp = nt * 16 + n;
@@ -722,7 +731,7 @@ __global__ __launch_bounds__(256) void ir_block_kernel(IrArgs a)
         // depthwise: 64 pixels x 16 channel groups, 4 per thread
         float wk[40];
 #pragma unroll
-        for (int i = 0; i < 40; ++i) wk[i] = wl[4 * c4 * 10 + i];
+        for (int i = 0; i < 40; ++i) wk[i] = wl[(q * kIrChunk + 4 * c4) * 10 + i];
 #pragma unroll 1
         for (int j = 0; j < 4; ++j) {
             const int px = (threadIdx.x >> 4) + 16 * j, ty = px >> 3, tx = px & 7;
@@ -754,6 +763,12 @@ __global__ __launch_bounds__(256) void ir_block_kernel(IrArgs a)
                 for (int j = 0; j < MPW; ++j) acc2[j][nt] = mfma(wb[j][ks], b, acc2[j][nt]);
             }
         }
+#pragma unroll
+        for (int ks = 0; ks < KSe; ++ks) wa[ks] = wa_n[ks];
+#pragma unroll
+        for (int j = 0; j < MPW; ++j)
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) wb[j][ks] = wb_n[j][ks];
     }
 
     // h_out = h + Wc v + bc
@@ -1096,9 +1111,8 @@ hipError_t launch_planes(const uint16_t* m, int64_t pitch, int64_t img_stride, i
 
 size_t ir_lds_bytes(int ch, int x)
 {
-    (void)x;
     return (size_t)(kIrRows * (ch + 8) + kIrRows * kIrLd + kIrT * kIrT * kIrLd) * sizeof(uint16_t) +
-           kIrChunk * 11 * sizeof(float);
+           (size_t)x * 11 * sizeof(float);
 }
 
 bool ir_fused_ok(int ch, int x)
