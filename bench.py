@@ -538,8 +538,8 @@ def main():
                     help="only run a plain device copy of MB megabytes (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the path shards by frame pairs/streams; "
-              "see the design notes); got --gpus %d" % args.gpus, file=sys.stderr)
+        print("bench.py: runs on one GPU only (the path shards by frame pairs and streams, "
+              "with no exchange step); got --gpus %d" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

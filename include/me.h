@@ -54,7 +54,7 @@ extern "C" {
 typedef enum {
     ME_OK = 0,
     ME_E_INVAL = 1,        /* bad argument: null pointer, bad size, inconsistent geometry */
-    ME_E_UNSUPPORTED = 2,  /* valid request this build does not implement (e.g. B=12) */
+    ME_E_UNSUPPORTED = 2,  /* valid request the library does not implement (e.g. B=12) */
     ME_E_HIP = 3,          /* a HIP runtime call failed (no device, launch failure) */
     ME_E_NOMEM = 4,        /* device or host allocation failed */
     ME_E_STATE = 5         /* call not valid in the context's state (e.g. no weights loaded) */
@@ -78,7 +78,7 @@ typedef struct {
 typedef struct {
     int32_t block;                 /* B, packed pixels: 8, 16, 32 or 64 */
     int32_t radius;                /* R, candidates per side: 1..64 (full search: (2R+1)^2 candidates) */
-    int32_t step;                  /* candidate spacing; must be 1 in this build */
+    int32_t step;                  /* candidate spacing; me_estimate takes 1 (me_stage_search any) */
     int32_t mode;                  /* me_mode */
     int32_t refine_radius;         /* proposal mode: exact search radius around the proposal (0..8) */
     float conf_logit_thresh;       /* proposal mode: fall back when logit < this (0 <=> confidence 0.5) */
@@ -341,7 +341,7 @@ me_status me_autotune(me_ctx ctx, const me_frame* ref, const me_frame* cur, int3
  * Perception residual network (PRNet, paper Sec. 3.3): corrects propagated
  * features, z_out = z_pred + r with r = PRNet(current frame, z_pred), trained
  * on the residual z_C - z_pred with a region-weighted reverse Huber (BerHu)
- * loss.  The paper gives the parts but no widths; this build's network:
+ * loss.  The paper gives the parts but no widths; the network here:
  *   encoder: two depthwise-separable blocks over the current frame's packed
  *     planes ((v - 2048) / 1024): depthwise 3x3 stride 2 (+bias, ReLU6), then
  *     1x1 to c_enc channels (+bias, ReLU6); output on the feature grid

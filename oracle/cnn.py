@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-The proposal network is this build's addition to the paper's method: the
+The proposal network is an addition to the paper's method: the
 paper's learned part corrects propagated features (PRNet, Sec. 3.3), while
 here a small CNN proposes one vector per block that an exact search refines.
 What the paper fixes and this reuses:

@@ -6,7 +6,7 @@ displacement ``d`` is a mosaic displacement ``2d`` (even offsets keep the
 colour phase).  Agreement with the oracle, which works on packed planes, thus
 also checks the packed-plane identity.  Selection is Python's tuple order on
 ``(SAD, dx^2 + dy^2, dy, dx)`` -- the paper's lowest-SAD rule (Sec. 3.2) with
-the tie-break taken for this build.
+the tie-break taken here (lowest SAD, then smallest squared length, dy, dx).
 """
 
 
