@@ -714,7 +714,7 @@ __global__ __launch_bounds__(256) void ir_block_kernel(IrArgs a)
         const int oe = 16 * w + 4 * g;
         const float* bexp = wl + X * 10 + q * kIrChunk + oe;
         const float be0 = bexp[0], be1 = bexp[1], be2 = bexp[2], be3 = bexp[3];
-#pragma unroll 1
+#pragma unroll
         for (int nt = 0; nt < kIrRows / 16; ++nt) {
             const int hp = nt * 16 + n;
             const int gy = y0 + hp / kIrHW - 1, gx = x0 + hp % kIrHW - 1;
@@ -732,7 +732,7 @@ __global__ __launch_bounds__(256) void ir_block_kernel(IrArgs a)
         float wk[40];
 #pragma unroll
         for (int i = 0; i < 40; ++i) wk[i] = wl[(q * kIrChunk + 4 * c4) * 10 + i];
-#pragma unroll 1
+#pragma unroll 2
         for (int j = 0; j < 4; ++j) {
             const int px = (threadIdx.x >> 4) + 16 * j, ty = px >> 3, tx = px & 7;
             float acc[4] = {wk[9], wk[19], wk[29], wk[39]};
