@@ -238,17 +238,16 @@ def gop_leg(me, ctx, frames, B, R, args):
 def prnet_bytes(cfg, Hb, Wb, n=1, zbytes=4):
     """HBM bytes of one forward pass of the residual network as scheduled
     here: every kernel reads its inputs and writes its output once
-    (activations bfloat16, features zbytes per element); each inverted
-    residual block is one kernel that reads h and writes h (its expanded
-    activations stay in LDS); weights once.  Returns (schedule bytes,
+    (activations bfloat16, features zbytes per element); the encoder and each
+    inverted residual block are one kernel each (their intermediates stay in
+    LDS); weights once.  Returns (schedule bytes,
     compulsory bytes = frame + z_pred + z_out + weights)."""
     Hp, Wp = Hb // 2, Wb // 2
     H1, W1 = (Hp + 1) // 2, (Wp + 1) // 2
     Hf, Wf = (H1 + 1) // 2, (W1 + 1) // 2
     P0, P1, P2 = n * Hp * Wp, n * H1 * W1, n * Hf * Wf
     e, h, x, cz = cfg.c_enc, cfg.c_hid, cfg.c_hid * cfg.expand, cfg.c_feat
-    act = [P0 * 4 * 2 + P0 * 4 * 2]                           # mosaic in, planes out
-    act += [P0 * 4 * 2 + P1 * 4 * 2, P1 * 4 * 2 + P1 * e * 2, P1 * e * 2 + P2 * e * 2, P2 * e * 4]
+    act = [P0 * 4 * 2 + P2 * e * 2]                           # fused encoder: mosaic in, encoder output out
     act += [P2 * cz * zbytes + P2 * cz * 2]                   # z_pred to channels-last bfloat16
     act += [P2 * cz * 2 + P2 * e * 2 + P2 * h * 2]            # projection
     act += [cfg.n_blocks * 2 * P2 * h * 2]                    # fused blocks

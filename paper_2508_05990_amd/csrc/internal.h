@@ -193,6 +193,21 @@ struct IrArgs {
     int32_t n, Hf, Wf, ch, x;
 };
 bool ir_fused_ok(int ch, int x);
+
+// The encoder fused (inference): packed planes of the mosaic, depthwise s2 +
+// ReLU6 (4 channels), 1x1 4 -> ce + ReLU6, depthwise s2 + ReLU6, 1x1 ce -> ce
+// + ReLU6, written as bfloat16 channels-last [n][Hf][Wf][ce].  Float32 master
+// parameters of the four layers; w3p: packed A operand of the last 1x1.
+struct EncArgs {
+    const uint16_t* mosaic;
+    int64_t pitch, img_stride;
+    int32_t n, Hp, Wp, H1, W1, Hf, Wf, ce;
+    const float *w0, *b0, *w1, *b1, *w2, *b2, *b3;
+    const uint16_t* w3p;
+    uint16_t* out;
+};
+bool enc_fused_ok(int ce);
+hipError_t launch_encoder(const EncArgs& a, hipStream_t st);
 hipError_t launch_ir_block(const IrArgs& a, hipStream_t st);
 hipError_t launch_to_nhwc(const void* src, int f32, int n, int C, int HW, uint16_t* dst, hipStream_t st);
 int prloss_blocks(int P);

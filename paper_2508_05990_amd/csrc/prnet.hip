@@ -791,6 +791,136 @@ __global__ __launch_bounds__(256) void ir_block_kernel(IrArgs a)
     }
 }
 
+// ---------------------------------------------------------- fused encoder --
+
+// One workgroup per 8 x 8 tile of encoder outputs.  Working backwards from the
+// tile: the second depthwise layer (stride 2) needs e2 on 17 x 17 positions,
+// which the first 1x1 makes pointwise from e1 on the same positions, which the
+// first depthwise layer (stride 2) makes from the packed planes on 35 x 35
+// positions.  Every intermediate stays in LDS (float32 holding the bfloat16
+// values the layer-by-layer path stores; zero outside the image, the zero
+// padding of the next depthwise layer); the last 1x1 runs on MFMA.
+constexpr int kEncT = 8, kEncE2 = 2 * kEncT + 1, kEncA0 = 2 * kEncE2 + 1;
+
+__global__ __launch_bounds__(256) void encoder_kernel(EncArgs a)
+{
+    extern __shared__ __align__(16) float fl[];
+    const int CE = a.ce;
+    float* a0 = fl;                                        // [35 * 35][4]
+    float* e1 = a0 + kEncA0 * kEncA0 * 4;                  // [17 * 17][4]
+    float* e2 = e1 + kEncE2 * kEncE2 * 4;                  // [17 * 17][CE]
+    float* wv = e2 + kEncE2 * kEncE2 * CE;                 // w0 [4][9], b0 [4], w1 [CE][4], b1, w2 [CE][9], b2, b3
+    float* w0 = wv;
+    float* b0 = w0 + 36;
+    float* w1 = b0 + 4;
+    float* b1 = w1 + CE * 4;
+    float* w2 = b1 + CE;
+    float* b2 = w2 + CE * 9;
+    float* b3 = b2 + CE;
+    const int ldc = CE + 8;
+    uint16_t* e3 = reinterpret_cast<uint16_t*>(b3 + CE);  // [64][CE + 8] bfloat16 (MFMA B operand rows)
+
+    const int tiles_x = (a.Wf + kEncT - 1) / kEncT, tiles_y = (a.Hf + kEncT - 1) / kEncT;
+    const int img = blockIdx.x / (tiles_x * tiles_y), tr = blockIdx.x - img * tiles_x * tiles_y;
+    const int Y0 = (tr / tiles_x) * kEncT, X0 = (tr % tiles_x) * kEncT;
+    const int tid = threadIdx.x, nt = blockDim.x;
+
+    for (int e = tid; e < 40 + CE * 15 + CE; e += nt) {
+        float v;
+        if (e < 36) v = a.w0[e];
+        else if (e < 40) v = a.b0[e - 36];
+        else if (e < 40 + CE * 4) v = bf2f(f2bf(a.w1[e - 40]));           // the 1x1 weights are used as bfloat16
+        else if (e < 40 + CE * 5) v = a.b1[e - 40 - CE * 4];
+        else if (e < 40 + CE * 14) v = a.w2[e - 40 - CE * 5];
+        else if (e < 40 + CE * 15) v = a.b2[e - 40 - CE * 14];
+        else v = a.b3[e - 40 - CE * 15];
+        wv[e] = v;
+    }
+    // packed planes (v - 2048) / 1024 on 35 x 35 positions from packed (4 Y0 - 3, 4 X0 - 3)
+    const uint16_t* m = a.mosaic + img * a.img_stride;
+    for (int e = tid; e < kEncA0 * kEncA0; e += nt) {
+        const int r = e / kEncA0, c = e - r * kEncA0;
+        const int py = 4 * Y0 - 3 + r, px = 4 * X0 - 3 + c;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (py >= 0 && py < a.Hp && px >= 0 && px < a.Wp) {
+            const uint16_t* q = m + (int64_t)(2 * py) * a.pitch + 2 * px;
+            const float k = 1.f / 1024.f;
+            v = unpack4(pack4(((float)q[0] - 2048.f) * k, ((float)q[1] - 2048.f) * k, ((float)q[a.pitch] - 2048.f) * k,
+                              ((float)q[a.pitch + 1] - 2048.f) * k));
+        }
+        *reinterpret_cast<float4*>(a0 + 4 * e) = v;
+    }
+    __syncthreads();
+    // e1: depthwise stride 2 of the planes on 17 x 17 positions from (2 Y0 - 1, 2 X0 - 1)
+    for (int e = tid; e < kEncE2 * kEncE2; e += nt) {
+        const int r = e / kEncE2, c = e - r * kEncE2;
+        const int gy = 2 * Y0 - 1 + r, gx = 2 * X0 - 1 + c;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (gy >= 0 && gy < a.H1 && gx >= 0 && gx < a.W1) {
+            float acc[4] = {b0[0], b0[1], b0[2], b0[3]};
+#pragma unroll
+            for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+                for (int kx = 0; kx < 3; ++kx) {
+                    const float4 x = *reinterpret_cast<const float4*>(a0 + 4 * ((2 * r + ky) * kEncA0 + 2 * c + kx));
+                    const int t = 3 * ky + kx;
+                    acc[0] += w0[t] * x.x;
+                    acc[1] += w0[9 + t] * x.y;
+                    acc[2] += w0[18 + t] * x.z;
+                    acc[3] += w0[27 + t] * x.w;
+                }
+            v = unpack4(pack4(relu6f(acc[0]), relu6f(acc[1]), relu6f(acc[2]), relu6f(acc[3])));
+        }
+        *reinterpret_cast<float4*>(e1 + 4 * e) = v;
+    }
+    __syncthreads();
+    // e2: 1x1 4 -> CE on the same positions (zero outside the image)
+    for (int e = tid; e < kEncE2 * kEncE2 * CE; e += nt) {
+        const int p = e / CE, o = e - p * CE;
+        const int r = p / kEncE2, c = p - r * kEncE2;
+        const int gy = 2 * Y0 - 1 + r, gx = 2 * X0 - 1 + c;
+        float v = 0.f;
+        if (gy >= 0 && gy < a.H1 && gx >= 0 && gx < a.W1) {
+            const float4 x = *reinterpret_cast<const float4*>(e1 + 4 * p);
+            const float* w = w1 + 4 * o;
+            v = bf2f(f2bf(relu6f(b1[o] + w[0] * x.x + w[1] * x.y + w[2] * x.z + w[3] * x.w)));
+        }
+        e2[e] = v;
+    }
+    __syncthreads();
+    // e3: depthwise stride 2 on the 8 x 8 tile, bfloat16 rows for the MFMA
+    for (int e = tid; e < kEncT * kEncT * CE; e += nt) {
+        const int p = e / CE, o = e - p * CE;
+        const int ty = p >> 3, tx = p & 7;
+        float acc = b2[o];
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) acc += w2[o * 9 + 3 * ky + kx] * e2[((2 * ty + ky) * kEncE2 + 2 * tx + kx) * CE + o];
+        e3[p * ldc + o] = f2bf(relu6f(acc));
+    }
+    for (int e = tid; e < kEncT * kEncT * 8; e += nt) e3[(e >> 3) * ldc + CE + (e & 7)] = 0;
+    __syncthreads();
+    // e4: 1x1 CE -> CE on MFMA; wave w takes pixels 16 w .. 16 w + 15
+    const int lane = tid & 63, w = tid >> 6, g = lane >> 4, n = lane & 15;
+    const int KS = (CE + 15) >> 4, MT = (CE + 15) >> 4;
+    const uint2* wp = reinterpret_cast<const uint2*>(a.w3p);
+    const uint16_t* brow = e3 + (16 * w + n) * ldc + 4 * g;
+    const int px = 16 * w + n, Y = Y0 + (px >> 3), X = X0 + (px & 7);
+    const bool inside = Y < a.Hf && X < a.Wf;
+    uint2* out = reinterpret_cast<uint2*>(a.out) + ((size_t)img * a.Hf * a.Wf + (size_t)Y * a.Wf + X) * (CE >> 2);
+    for (int t = 0; t < MT; ++t) {
+        v4f32 acc = (v4f32){0.f, 0.f, 0.f, 0.f};
+        for (int ks = 0; ks < KS; ++ks)
+            acc = mfma(as_v4(wp[((size_t)t * KS + ks) * 64 + lane]), as_v4(*reinterpret_cast<const uint2*>(brow + 16 * ks)),
+                       acc);
+        const int o = 16 * t + 4 * g;
+        if (inside && o < CE)
+            out[o >> 2] = pack4(relu6f(acc[0] + b3[o]), relu6f(acc[1] + b3[o + 1]), relu6f(acc[2] + b3[o + 2]),
+                                relu6f(acc[3] + b3[o + 3]));
+    }
+}
+
 // -------------------------------------------------------------- layout --
 
 // [n][C][HW] (float32 or bfloat16) -> [n][HW][C] bfloat16, through a 64 x 64 LDS
@@ -1136,6 +1266,26 @@ hipError_t launch_ir_block(const IrArgs& a, hipStream_t st)
     case 128: hipLaunchKernelGGL(ir_block_kernel<128>, dim3(tiles), dim3(256), lds, st, a); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+static size_t enc_lds_bytes(int ce)
+{
+    return (size_t)(kEncA0 * kEncA0 * 4 + kEncE2 * kEncE2 * 4 + kEncE2 * kEncE2 * ce + 40 + ce * 16) * sizeof(float) +
+           (size_t)kEncT * kEncT * (ce + 8) * sizeof(uint16_t);
+}
+
+bool enc_fused_ok(int ce) { return ce % 16 == 0 && ce <= 128 && enc_lds_bytes(ce) <= 158 * 1024; }
+
+hipError_t launch_encoder(const EncArgs& a, hipStream_t st)
+{
+    if (!enc_fused_ok(a.ce)) return hipErrorInvalidValue;
+    const int tiles = a.n * div_up(a.Hf, kEncT) * div_up(a.Wf, kEncT);
+    if (tiles == 0) return hipSuccess;
+    const size_t lds = enc_lds_bytes(a.ce);
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(encoder_kernel), lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(encoder_kernel, dim3(tiles), dim3(256), lds, st, a);
     return hipGetLastError();
 }
 

@@ -301,15 +301,42 @@ hipError_t run_forward(me_prnet net, const me_frame* cur, int64_t frame_stride, 
     const int n = net->n, HW1 = net->H1 * net->W1, HW2 = net->Hf * net->Wf;
     const int P1 = n * HW1, P2 = n * HW2;
     const std::vector<Layer>& L = net->L;
-    hipError_t e = launch_planes(cur->data, cur->pitch, frame_stride, n, net->Hp, net->Wp, net->a0, st);
-    if (e == hipSuccess)
-        e = launch_dw_fwd(net->a0, net->params + L[0].off_w, net->params + L[0].off_b, net->e1, n, net->Hp, net->Wp, 4,
-                          2, 1, st);
-    if (e == hipSuccess) e = launch_pw(pw_args(net, L[1], nhwc(net->e1, 4), none(), HW1, P1, net->e2), st);
-    if (e == hipSuccess)
-        e = launch_dw_fwd(net->e2, net->params + L[2].off_w, net->params + L[2].off_b, net->e3, n, net->H1, net->W1,
-                          c.c_enc, 2, 1, st);
-    if (e == hipSuccess) e = launch_pw(pw_args(net, L[3], nhwc(net->e3, c.c_enc), none(), HW2, P2, net->e4), st);
+    hipError_t e = hipSuccess;
+    if (!train && enc_fused_ok(c.c_enc)) {
+        // inference: the whole encoder in one pass (its intermediates are not kept)
+        EncArgs ea{};
+        ea.mosaic = cur->data;
+        ea.pitch = cur->pitch;
+        ea.img_stride = frame_stride;
+        ea.n = n;
+        ea.Hp = net->Hp;
+        ea.Wp = net->Wp;
+        ea.H1 = net->H1;
+        ea.W1 = net->W1;
+        ea.Hf = net->Hf;
+        ea.Wf = net->Wf;
+        ea.ce = c.c_enc;
+        ea.w0 = net->params + L[0].off_w;
+        ea.b0 = net->params + L[0].off_b;
+        ea.w1 = net->params + L[1].off_w;
+        ea.b1 = net->params + L[1].off_b;
+        ea.w2 = net->params + L[2].off_w;
+        ea.b2 = net->params + L[2].off_b;
+        ea.w3p = net->packs + L[3].fwd;
+        ea.b3 = net->params + L[3].off_b;
+        ea.out = net->e4;
+        e = launch_encoder(ea, st);
+    } else {
+        e = launch_planes(cur->data, cur->pitch, frame_stride, n, net->Hp, net->Wp, net->a0, st);
+        if (e == hipSuccess)
+            e = launch_dw_fwd(net->a0, net->params + L[0].off_w, net->params + L[0].off_b, net->e1, n, net->Hp,
+                              net->Wp, 4, 2, 1, st);
+        if (e == hipSuccess) e = launch_pw(pw_args(net, L[1], nhwc(net->e1, 4), none(), HW1, P1, net->e2), st);
+        if (e == hipSuccess)
+            e = launch_dw_fwd(net->e2, net->params + L[2].off_w, net->params + L[2].off_b, net->e3, n, net->H1,
+                              net->W1, c.c_enc, 2, 1, st);
+        if (e == hipSuccess) e = launch_pw(pw_args(net, L[3], nhwc(net->e3, c.c_enc), none(), HW2, P2, net->e4), st);
+    }
     const PwTensor z{zp, c.c_feat, 1, z_bf16 ? 0 : 1};
     if (e == hipSuccess) e = launch_to_nhwc(zp, z_bf16 ? 0 : 1, n, c.c_feat, HW2, net->zl, st);
     if (e == hipSuccess)
