@@ -248,8 +248,7 @@ def prnet_bytes(cfg, Hb, Wb, n=1, zbytes=4):
     P0, P1, P2 = n * Hp * Wp, n * H1 * W1, n * Hf * Wf
     e, h, x, cz = cfg.c_enc, cfg.c_hid, cfg.c_hid * cfg.expand, cfg.c_feat
     act = [P0 * 4 * 2 + P2 * e * 2]                           # fused encoder: mosaic in, encoder output out
-    act += [P2 * cz * zbytes + P2 * cz * 2]                   # z_pred to channels-last bfloat16
-    act += [P2 * cz * 2 + P2 * e * 2 + P2 * h * 2]            # projection
+    act += [P2 * cz * zbytes + P2 * e * 2 + P2 * h * 2]       # projection: z_pred (channels-first), encoder -> h0
     act += [cfg.n_blocks * 2 * P2 * h * 2]                    # fused blocks
     act += [P2 * h * 2 + 2 * P2 * cz * zbytes]                # head: reads h and z_pred, writes z_out
     params = 4 * 9 + 4 + 4 * e + e + e * 9 + e + e * e + e + (cz + e) * h + h + \

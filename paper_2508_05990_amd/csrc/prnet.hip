@@ -93,6 +93,32 @@ __device__ void stage_rows(const PwTensor& t, int koff, int p0, int P, int HW, u
             }
             *reinterpret_cast<uint2*>(lds + px * ldk + koff + 4 * c4) = v;
         }
+    } else if ((HW & 3) == 0) {
+        // channels-first, four pixels per thread (a group never straddles two images):
+        // 16 lanes cover a 64-pixel channel row
+        for (int e = threadIdx.x; e < (kPx / 4) * t.C; e += blockDim.x) {
+            const int c = e >> 4, q = e & 15, p = p0 + 4 * q;
+            float v[4] = {0.f, 0.f, 0.f, 0.f};
+            if (p < P) {
+                const int img = p / HW, hw = p - img * HW;
+                const size_t idx = ((size_t)img * t.C + c) * HW + hw;
+                if (t.f32) {
+                    const float4 f = *reinterpret_cast<const float4*>(static_cast<const float*>(t.p) + idx);
+                    v[0] = f.x;
+                    v[1] = f.y;
+                    v[2] = f.z;
+                    v[3] = f.w;
+                } else {
+                    const float4 f = unpack4(*reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(t.p) + idx));
+                    v[0] = f.x;
+                    v[1] = f.y;
+                    v[2] = f.z;
+                    v[3] = f.w;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) lds[(4 * q + i) * ldk + koff + c] = f2bf(v[i]);
+        }
     } else {
         for (int e = threadIdx.x; e < kPx * t.C; e += blockDim.x) {
             const int c = e / kPx, px = e - c * kPx, p = p0 + px;
@@ -166,7 +192,7 @@ __host__ __device__ inline bool pw_chw_fast(const PwArgs& a)
 __global__ __launch_bounds__(256) void pw_kernel(PwArgs a)
 {
     extern __shared__ __align__(16) uint16_t lds[];
-    const int K = a.KS * 16, ldk = K + 8;
+    const int K = a.KS * 16, ldk = K + 4;   // rows 8-byte aligned, 18 mod 64 banks apart
     const int MT = (a.M + 15) >> 4;
     uint16_t* xl = lds;
     const uint2* wp = reinterpret_cast<const uint2*>(a.w);
@@ -1103,7 +1129,7 @@ __global__ void prloss_sum_kernel(const float* __restrict__ partial, int m, floa
 
 // ------------------------------------------------------------ host side --
 
-size_t pw_lds_bytes(int KS) { return (size_t)kPx * (KS * 16 + 8) * sizeof(uint16_t); }
+size_t pw_lds_bytes(int KS) { return (size_t)kPx * (KS * 16 + 4) * sizeof(uint16_t); }
 
 size_t pw_wgrad_lds_bytes(int cin, int cout)
 {

@@ -338,9 +338,15 @@ hipError_t run_forward(me_prnet net, const me_frame* cur, int64_t frame_stride, 
         if (e == hipSuccess) e = launch_pw(pw_args(net, L[3], nhwc(net->e3, c.c_enc), none(), HW2, P2, net->e4), st);
     }
     const PwTensor z{zp, c.c_feat, 1, z_bf16 ? 0 : 1};
-    if (e == hipSuccess) e = launch_to_nhwc(zp, z_bf16 ? 0 : 1, n, c.c_feat, HW2, net->zl, st);
-    if (e == hipSuccess)
-        e = launch_pw(pw_args(net, L[4], nhwc(net->zl, c.c_feat), nhwc(net->e4, c.c_enc), HW2, P2, net->h[0]), st);
+    if (train || (HW2 & 3)) {
+        // channels-last copy of z_pred (kept for the projection's weight gradient)
+        if (e == hipSuccess) e = launch_to_nhwc(zp, z_bf16 ? 0 : 1, n, c.c_feat, HW2, net->zl, st);
+        if (e == hipSuccess)
+            e = launch_pw(pw_args(net, L[4], nhwc(net->zl, c.c_feat), nhwc(net->e4, c.c_enc), HW2, P2, net->h[0]), st);
+    } else if (e == hipSuccess) {
+        // inference: the projection stages z_pred straight from its channels-first layout
+        e = launch_pw(pw_args(net, L[4], z, nhwc(net->e4, c.c_enc), HW2, P2, net->h[0]), st);
+    }
     const int X = c.c_hid * c.expand;
     const bool fused = !train && ir_fused_ok(c.c_hid, X);   // training keeps u and v for the backward pass
     for (int k = 0; k < c.n_blocks && e == hipSuccess; ++k) {
