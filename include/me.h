@@ -331,7 +331,9 @@ me_status me_batch_submit(me_ctx ctx, const me_job* jobs, int32_t n, void* strea
  * (candidate tile shape per lane, blocks per workgroup, LDS window band) on
  * this frame pair with HIP events and keep the fastest in the context for
  * (block, radius, frame size); later me_estimate calls with that key use it.
- * Every shape gives bit-identical results.  Synchronises `stream`.
+ * Every shape gives bit-identical results.  Synchronises `stream`; a batch
+ * graph captured earlier in the context is dropped (the next me_batch_submit
+ * records the tuned shapes).
  * best_ms (host, may be NULL) receives the fastest mean time of `iters` runs.
  */
 me_status me_autotune(me_ctx ctx, const me_frame* ref, const me_frame* cur, int32_t block, int32_t radius,

@@ -723,6 +723,14 @@ me_status me_autotune(me_ctx ctx, const me_frame* ref, const me_frame* cur, int3
         std::lock_guard<std::mutex> g(ctx->mu);
         ctx->tuned[std::make_tuple(block, radius, Hp, Wp)] = best_cfg;
     }
+    // a captured batch graph holds the launch shapes it was recorded with: drop
+    // it so that the next submission records the tuned shape
+    if (ctx->graph) {
+        if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "me_autotune: synchronize");
+        (void)hipGraphExecDestroy(ctx->graph);
+        ctx->graph = nullptr;
+    }
+    ctx->batch_shapes.clear();
     if (best_ms) *best_ms = best;
     return ME_OK;
 }

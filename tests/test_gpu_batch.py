@@ -139,3 +139,42 @@ def test_autotune_keeps_results(dev, oracle_mod):
         assert torch.equal(mv0, mv1) and torch.equal(sad0, sad1)
     finally:
         ctx.close()
+
+
+def test_autotune_after_batch_recaptures(dev):
+    """A batch graph recorded before the autotuner runs is dropped by it; the
+    next submission records the tuned launch shapes and gives the same
+    vectors and SADs as before tuning."""
+    import torch
+
+    from paper_2508_05990_amd import synth
+
+    ctx = dev.Context(0)
+    try:
+        jobs = []
+        for B, R, seq in list(synth.stream_sequences(3, n_frames=2))[:6]:
+            f0, f1 = (torch.from_numpy(f).cuda() for f in seq.frames)
+            bh, bw = dev.block_grid(*seq.shape, B)
+            jobs.append((f0, f1, B, R, torch.full((bh, bw, 2), 99, dtype=torch.int16, device="cuda"),
+                         torch.full((bh, bw), -9, dtype=torch.int32, device="cuda")))
+        arr = dev.make_jobs(jobs)
+        print("submission before tuning", flush=True)
+        dev.batch_submit(ctx, arr)
+        torch.cuda.synchronize()
+        before = [(j[4].clone(), j[5].clone()) for j in jobs]
+        seen = set()
+        for f0, f1, B, R, _, _ in jobs:
+            if (B, R) + tuple(f0.shape) not in seen:
+                seen.add((B, R) + tuple(f0.shape))
+                print("autotune", B, R, tuple(f0.shape), flush=True)
+                dev.autotune(ctx, f0, f1, B, R, iters=1)
+        for j in jobs:
+            j[4].fill_(99)
+            j[5].fill_(-9)
+        print("submission after tuning", flush=True)
+        dev.batch_submit(ctx, arr)
+        torch.cuda.synchronize()
+        for k, (j, (mv, sad)) in enumerate(zip(jobs, before)):
+            assert torch.equal(j[4], mv) and torch.equal(j[5], sad), (k, j[2], j[3], tuple(j[0].shape))
+    finally:
+        ctx.close()
