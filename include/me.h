@@ -339,6 +339,31 @@ me_status me_batch_submit(me_ctx ctx, const me_job* jobs, int32_t n, void* strea
 me_status me_autotune(me_ctx ctx, const me_frame* ref, const me_frame* cur, int32_t block, int32_t radius,
                       int32_t iters, float* best_ms, void* stream);
 
+/*
+ * me_tuned_shape -- the launch shape the context uses for a full search with
+ * (block, radius) on height x width Bayer frames (batch grid of Sec. 4.1):
+ * shape[0] candidates per lane along x, shape[1] along y, shape[2] blocks per
+ * workgroup, shape[3] the LDS window size in KB (rounded up).  *tuned (may be
+ * NULL) is 1 when the shape was recorded by me_autotune or
+ * me_set_tuned_shape, 0 when it is the built-in default.  Host call, no GPU
+ * work.  ME_E_INVAL on a null pointer, odd or empty frame or radius outside
+ * [0, 64]; ME_E_UNSUPPORTED on a block size outside {8, 16, 32, 64}.
+ *
+ * me_set_tuned_shape -- record a shape in that form (for instance one that
+ * me_tuned_shape reported in an earlier process, so that tuning persists):
+ * shape[3] is the LDS budget in KB; the window band is the largest that fits
+ * it, so a reported shape set back gives the same launch.  Results do not
+ * depend on the shape.  ME_E_UNSUPPORTED when the tile is not compiled for
+ * the block size, blocks per workgroup is not 1 (or 2 with radius % 4 == 0),
+ * or no band fits the budget (at most 158 KB); the stored table is unchanged
+ * then.  Drops a batch graph captured earlier in the context, synchronising
+ * the device first.
+ */
+me_status me_tuned_shape(me_ctx ctx, int32_t block, int32_t radius, int32_t height, int32_t width, int32_t* shape,
+                         int32_t* tuned);
+me_status me_set_tuned_shape(me_ctx ctx, int32_t block, int32_t radius, int32_t height, int32_t width,
+                             const int32_t* shape);
+
 /* ------------------------------------------------------------------------
  * Perception residual network (PRNet, paper Sec. 3.3): corrects propagated
  * features, z_out = z_pred + r with r = PRNet(current frame, z_pred), trained

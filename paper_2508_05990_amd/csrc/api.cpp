@@ -651,6 +651,26 @@ me_status me_batch_submit(me_ctx ctx, const me_job* jobs, int32_t n, void* strea
     return ME_OK;
 }
 
+// Records `c` as the launch shape for (block, radius, Hp, Wp).  A captured batch
+// graph holds the shapes it was recorded with: it is dropped, so the next
+// submission records the new one.
+static me_status store_shape(me_ctx ctx, int block, int radius, int Hp, int Wp, const TileCfg& c, const char* who)
+{
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        ctx->tuned[std::make_tuple(block, radius, Hp, Wp)] = c;
+    }
+    if (ctx->graph) {
+        hipError_t e = hipSetDevice(ctx->device);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, who);
+        (void)hipGraphExecDestroy(ctx->graph);
+        ctx->graph = nullptr;
+    }
+    ctx->batch_shapes.clear();
+    return ME_OK;
+}
+
 me_status me_autotune(me_ctx ctx, const me_frame* ref, const me_frame* cur, int32_t block, int32_t radius,
                       int32_t iters, float* best_ms, void* stream)
 {
@@ -719,20 +739,60 @@ me_status me_autotune(me_ctx ctx, const me_frame* ref, const me_frame* cur, int3
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     if (e != hipSuccess) return hip_fail(e, "me_autotune: timing");
-    {
-        std::lock_guard<std::mutex> g(ctx->mu);
-        ctx->tuned[std::make_tuple(block, radius, Hp, Wp)] = best_cfg;
-    }
-    // a captured batch graph holds the launch shapes it was recorded with: drop
-    // it so that the next submission records the tuned shape
-    if (ctx->graph) {
-        if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "me_autotune: synchronize");
-        (void)hipGraphExecDestroy(ctx->graph);
-        ctx->graph = nullptr;
-    }
-    ctx->batch_shapes.clear();
+    if ((s = store_shape(ctx, block, radius, Hp, Wp, best_cfg, "me_autotune")) != ME_OK) return s;
     if (best_ms) *best_ms = best;
     return ME_OK;
+}
+
+me_status me_tuned_shape(me_ctx ctx, int32_t block, int32_t radius, int32_t height, int32_t width, int32_t* shape,
+                         int32_t* tuned)
+{
+    if (!ctx || !shape) return fail(ME_E_INVAL, "me_tuned_shape: null context or shape");
+    if (!block_ok(block)) return fail(ME_E_UNSUPPORTED, "me_tuned_shape: block %d not in {8,16,32,64}", block);
+    if (radius < 0 || radius > 64) return fail(ME_E_INVAL, "me_tuned_shape: radius %d not in [0,64]", radius);
+    if (height < 2 || width < 2 || (height & 1) || (width & 1))
+        return fail(ME_E_INVAL, "me_tuned_shape: frame %dx%d not even and positive", height, width);
+    const int Hp = height / 2, Wp = width / 2;
+    bool found = false;
+    TileCfg c{};
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        auto it = ctx->tuned.find(std::make_tuple(block, radius, Hp, Wp));
+        if (it != ctx->tuned.end()) {
+            c = it->second;
+            found = true;
+        }
+    }
+    if (!found) c = default_tiles(block, radius);
+    shape[0] = c.kx;
+    shape[1] = c.ky;
+    shape[2] = c.nb;
+    shape[3] = (int32_t)((c.lds_bytes + 1023) / 1024);
+    if (tuned) *tuned = found ? 1 : 0;
+    return ME_OK;
+}
+
+me_status me_set_tuned_shape(me_ctx ctx, int32_t block, int32_t radius, int32_t height, int32_t width,
+                             const int32_t* shape)
+{
+    if (!ctx || !shape) return fail(ME_E_INVAL, "me_set_tuned_shape: null context or shape");
+    if (!block_ok(block)) return fail(ME_E_UNSUPPORTED, "me_set_tuned_shape: block %d not in {8,16,32,64}", block);
+    if (radius < 0 || radius > 64) return fail(ME_E_INVAL, "me_set_tuned_shape: radius %d not in [0,64]", radius);
+    if (height < 2 || width < 2 || (height & 1) || (width & 1))
+        return fail(ME_E_INVAL, "me_set_tuned_shape: frame %dx%d not even and positive", height, width);
+    TileCfg c{};
+    c.kx = shape[0];
+    c.ky = shape[1];
+    c.nb = shape[2];
+    if (!tiles_supported(block, c.kx, c.ky))
+        return fail(ME_E_UNSUPPORTED, "me_set_tuned_shape: tile %dx%d not compiled for block %d", c.kx, c.ky, block);
+    if (c.nb < 1 || c.nb > 2 || (c.nb > 1 && radius % 4))
+        return fail(ME_E_UNSUPPORTED, "me_set_tuned_shape: %d blocks per workgroup (1, or 2 when radius %% 4 == 0)",
+                    c.nb);
+    if (shape[3] < 1 || shape[3] > 158 || !plan_tiles(block, radius, (size_t)shape[3] * 1024, &c))
+        return fail(ME_E_UNSUPPORTED, "me_set_tuned_shape: no window band fits in %d KB of LDS (at most 158)",
+                    shape[3]);
+    return store_shape(ctx, block, radius, height / 2, width / 2, c, "me_set_tuned_shape");
 }
 
 }  // extern "C"

@@ -902,7 +902,13 @@ TileCfg default_tiles(int B, int R)
 {
     TileCfg c{};
     c.kx = 4;
-    c.ky = 4;
+    // 4x4 tiles when the block is at least 16 wide and its main tiles give every
+    // wave of the block a full 64-lane task; otherwise 4x2 (more, shorter tasks
+    // and fewer registers: on 8-wide blocks, or radius 16 where 4x4 tiles make a
+    // single task for the block's four waves, 4x2 was faster in every measured
+    // frame size)
+    const int n = 2 * R + 1;
+    c.ky = (B >= 16 && (n / 4) * (n / 4) >= 64 * kWavesPerBlock) ? 4 : 2;
     // two blocks per workgroup share one window when the radius keeps their
     // window starts 16-byte aligned (R % 4 == 0) and the window fits in a
     // single band within 80 KB

@@ -79,6 +79,8 @@ _me_refine = _sig("me_refine", [_P, ctypes.POINTER(MeFrame), ctypes.POINTER(MeFr
                                 _P, _P, _P])
 _F = ctypes.c_float
 _me_autotune = _sig("me_autotune", [_P, ctypes.POINTER(MeFrame), ctypes.POINTER(MeFrame), _I32, _I32, _I32, _P, _P])
+_me_tuned_shape = _sig("me_tuned_shape", [_P, _I32, _I32, _I32, _I32, _P, _P])
+_me_set_tuned_shape = _sig("me_set_tuned_shape", [_P, _I32, _I32, _I32, _I32, _P])
 _me_cnn_set_params = _sig("me_cnn_set_params", [_P, _P, _I32, _F])
 _me_cnn_get_params = _sig("me_cnn_get_params", [_P, _P, _I32, _P])
 _me_cnn_pool = _sig("me_cnn_pool", [_P, ctypes.POINTER(MeFrame), ctypes.POINTER(MeFrame), _P, _P])
@@ -126,7 +128,8 @@ EXPORTS = ["me_default_params", "me_ctx_create", "me_ctx_destroy", "me_estimate"
            "me_warp_features", "me_batch_submit", "me_refine", "me_status_string", "me_last_error",
            "me_cnn_set_params", "me_cnn_get_params", "me_cnn_pool", "me_cnn_forward", "me_cnn_train_step",
            "me_cnn_state_bytes", "me_cnn_save_state", "me_cnn_load_state", "me_cnn_layer_forward",
-           "me_cnn_layer_backward", "me_cnn_loss", "me_cnn_adamw", "me_autotune", "me_pyramid",
+           "me_cnn_layer_backward", "me_cnn_loss", "me_cnn_adamw", "me_autotune", "me_tuned_shape",
+           "me_set_tuned_shape", "me_pyramid",
            "me_default_pyramid", "me_compose_vectors", "me_estimate_warp", "me_prnet_num_params", "me_prnet_create", "me_prnet_destroy",
            "me_prnet_set_params", "me_prnet_get_params", "me_prnet_forward", "me_prnet_train_step",
            "me_prnet_dw_forward", "me_prnet_dw_backward", "me_prnet_pw_forward", "me_prnet_pw_backward",
@@ -347,6 +350,23 @@ def autotune(ctx: Context, ref, cur, block=16, radius=32, iters=3, stream=None) 
     _check(_me_autotune(ctx.handle, ctypes.byref(fr), ctypes.byref(fc), block, radius, iters, ctypes.addressof(ms),
                         _stream_handle(stream)))
     return ms.value
+
+
+def tuned_shape(ctx: Context, block, radius, height, width):
+    """The launch shape used for (block, radius, height x width Bayer frames):
+    ((kx, ky, blocks per workgroup, LDS KB), tuned) with tuned True when it
+    was recorded by autotune or set_tuned_shape."""
+    shape = (ctypes.c_int32 * 4)()
+    tuned = ctypes.c_int32()
+    _check(_me_tuned_shape(ctx.handle, block, radius, height, width, ctypes.addressof(shape), ctypes.addressof(tuned)))
+    return tuple(shape), bool(tuned.value)
+
+
+def set_tuned_shape(ctx: Context, block, radius, height, width, shape):
+    """Record a launch shape (kx, ky, blocks per workgroup, LDS budget in KB)
+    for (block, radius, frame size), e.g. one reported by tuned_shape."""
+    arr = (ctypes.c_int32 * 4)(*[int(v) for v in shape])
+    _check(_me_set_tuned_shape(ctx.handle, block, radius, height, width, ctypes.addressof(arr)))
 
 
 def make_jobs(jobs):

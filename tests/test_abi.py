@@ -247,3 +247,23 @@ def test_estimate_warp_validation(me):
     q = me.default_params()
     q.block = 12
     assert me._me_estimate_warp(*args(q)) == me.ME_E_UNSUPPORTED
+
+
+def test_tuned_shape_validation(me):
+    fake = ctypes.c_void_p(FAKE)
+    out = (ctypes.c_int32 * 4)()
+    ok_shape = (ctypes.c_int32 * 4)(4, 4, 2, 80)
+    get = lambda ctx, b, r, h, w, o: me._me_tuned_shape(ctx, b, r, h, w, o, None)
+    assert get(None, 16, 32, 1080, 1920, ctypes.addressof(out)) == 1      # null context
+    assert get(fake, 16, 32, 1080, 1920, None) == 1                       # null shape
+    assert get(fake, 12, 32, 1080, 1920, ctypes.addressof(out)) == 2      # block size
+    assert get(fake, 16, 65, 1080, 1920, ctypes.addressof(out)) == 1      # radius
+    assert get(fake, 16, 32, 1081, 1920, ctypes.addressof(out)) == 1      # odd frame
+    put = lambda sh, b=16, r=32: me._me_set_tuned_shape(fake, b, r, 1080, 1920, ctypes.addressof(sh))
+    assert me._me_set_tuned_shape(None, 16, 32, 1080, 1920, ctypes.addressof(ok_shape)) == 1
+    assert put((ctypes.c_int32 * 4)(3, 4, 2, 80)) == 2                    # tile not compiled
+    assert put((ctypes.c_int32 * 4)(4, 4, 3, 80)) == 2                    # three blocks per workgroup
+    assert put((ctypes.c_int32 * 4)(4, 4, 2, 80), r=30) == 2              # two blocks need radius % 4 == 0
+    assert put((ctypes.c_int32 * 4)(4, 4, 1, 0)) == 2                     # no LDS budget
+    assert put((ctypes.c_int32 * 4)(4, 4, 1, 159)) == 2                   # beyond the LDS of a workgroup
+    assert put((ctypes.c_int32 * 4)(4, 4, 1, 1)) == 2                     # no band fits 1 KB

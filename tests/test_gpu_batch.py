@@ -178,3 +178,39 @@ def test_autotune_after_batch_recaptures(dev):
             assert torch.equal(j[4], mv) and torch.equal(j[5], sad), (k, j[2], j[3], tuple(j[0].shape))
     finally:
         ctx.close()
+
+
+def test_tuned_shape_report_and_restore(dev):
+    """tuned_shape reports the default (untuned) and then the autotuner's
+    choice; set in a second context it reads back unchanged; other shapes set
+    explicitly give the same vectors and SADs; a rejected shape leaves the
+    recorded one in place."""
+    import torch
+
+    from paper_2508_05990_amd import synth
+
+    seq = synth.hd_sequence(1, n_frames=2)
+    H, W = seq.shape
+    t0, t1 = (torch.from_numpy(f).cuda() for f in seq.frames)
+    ctx, ctx2 = dev.Context(0), dev.Context(0)
+    try:
+        sh0, tuned0 = dev.tuned_shape(ctx, 16, 32, H, W)
+        assert not tuned0 and sh0[:3] == (4, 4, 2) and 0 < sh0[3] <= 80
+        mv0, sad0 = dev.estimate(t0, t1, 16, 32, ctx=ctx)
+        dev.autotune(ctx, t0, t1, 16, 32, iters=1)
+        sh1, tuned1 = dev.tuned_shape(ctx, 16, 32, H, W)
+        assert tuned1
+        dev.set_tuned_shape(ctx2, 16, 32, H, W, sh1)
+        assert dev.tuned_shape(ctx2, 16, 32, H, W) == (sh1, True)
+        for shape in [(4, 4, 1, 53), (8, 2, 1, 80), (4, 1, 2, 158), (8, 4, 1, 30), sh1]:
+            print("shape", shape, flush=True)
+            dev.set_tuned_shape(ctx2, 16, 32, H, W, shape)
+            mv, sad = dev.estimate(t0, t1, 16, 32, ctx=ctx2)
+            torch.cuda.synchronize()
+            assert torch.equal(mv, mv0) and torch.equal(sad, sad0), shape
+        with pytest.raises(dev.MeError):
+            dev.set_tuned_shape(ctx2, 16, 32, H, W, (3, 4, 1, 80))
+        assert dev.tuned_shape(ctx2, 16, 32, H, W) == (sh1, True)
+    finally:
+        ctx.close()
+        ctx2.close()
