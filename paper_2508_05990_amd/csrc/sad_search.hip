@@ -142,12 +142,16 @@ __device__ __forceinline__ void write_result(const SearchArgs& a, int blk, uint6
 // LDS row r + 2j.  Walking the block rows of one parity in steps of 2, each
 // LDS row is loaded once and kept in a ring of KY segments for the KY
 // candidate rows that use it; the next ring slot and the next current-block
-// row are requested a step ahead of their use.
+// row are requested a step ahead of their use.  The current-block rows
+// alternate between two register sets by step parity (the unrolled steps
+// come in pairs), so a step's scalar load has the whole step to return and
+// no copy between the sets is needed.
 template <int CW, int NCH, int KX, int KY>
 __device__ __forceinline__ void tile_sads(cptr_t curp, int64_t cur_pitch, int h, const uint4* __restrict__ lbase4,
                                           int pitch4, uint32_t (&acc)[KY][KX])
 {
     constexpr int SEGV = (CW + KX - 1 + 3) / 4;
+    constexpr int KY2 = KY % 2 == 0 ? KY : 2 * KY;   // steps per unrolled group (even)
 #pragma unroll
     for (int j = 0; j < KY; ++j)
 #pragma unroll
@@ -159,46 +163,50 @@ __device__ __forceinline__ void tile_sads(cptr_t curp, int64_t cur_pitch, int h,
         for (int par = 0; par < 2; ++par) {
             const uint4* col4 = lbase4 + par * pitch4 + (q * CW) / 4;   // LDS row par, chunk q
             cptr_t ccol = curp + par * cur_pitch + q * CW;                 // block row par, chunk q
+            const int64_t rstep = 2 * cur_pitch;
             uint4 ring[KY][SEGV];
 #pragma unroll
             for (int t = 0; t < KY - 1; ++t)
 #pragma unroll
                 for (int v = 0; v < SEGV; ++v) ring[t][v] = col4[(2 * t) * pitch4 + v];
-            uint32_t c[CW];
+            uint32_t cA[CW], cB[CW];
 #pragma unroll
-            for (int k = 0; k < CW; ++k) c[k] = ccol[k];
+            for (int k = 0; k < CW; ++k) cA[k] = ccol[k];
+            cptr_t nxt = ccol + rstep;                     // block row par + 2 (st + 1)
+            // step st (u = st mod KY2): SADs against block row cu; block row par + 2 (st + 1)
+            // into cx (the last step reloads row par, which is in the block)
+            auto one = [&](const int u, const int st, const uint32_t(&cu)[CW], uint32_t(&cx)[CW]) {
+#pragma unroll
+                for (int v = 0; v < SEGV; ++v) ring[(u + KY - 1) % KY][v] = col4[(2 * (st + KY - 1)) * pitch4 + v];
+                const cptr_t src = st + 1 < h ? nxt : ccol;
+#pragma unroll
+                for (int k = 0; k < CW; ++k) cx[k] = src[k];
+                nxt += rstep;
+#pragma unroll
+                for (int j = 0; j < KY; ++j) {
+                    uint32_t seg[SEGV * 4];
+#pragma unroll
+                    for (int v = 0; v < SEGV; ++v) {
+                        const uint4 t4 = ring[(u + j) % KY][v];
+                        seg[4 * v + 0] = t4.x;
+                        seg[4 * v + 1] = t4.y;
+                        seg[4 * v + 2] = t4.z;
+                        seg[4 * v + 3] = t4.w;
+                    }
+#pragma unroll
+                    for (int k = 0; k < CW; ++k)
+#pragma unroll
+                        for (int i = 0; i < KX; ++i) acc[j][i] = __builtin_amdgcn_sad_u16(cu[k], seg[k + i], acc[j][i]);
+                }
+            };
 #pragma unroll 1
-            for (int step = 0; step < h; step += KY) {
+            for (int step = 0; step < h; step += KY2) {
 #pragma unroll
-                for (int u = 0; u < KY; ++u) {
+                for (int u = 0; u < KY2; ++u) {
                     const int st = step + u;               // block row par + 2 st
                     if (st < h) {
-#pragma unroll
-                        for (int v = 0; v < SEGV; ++v)
-                            ring[(u + KY - 1) % KY][v] = col4[(2 * (st + KY - 1)) * pitch4 + v];
-                        uint32_t cn[CW];
-                        const int stn = st + 1 < h ? st + 1 : st;
-#pragma unroll
-                        for (int k = 0; k < CW; ++k) cn[k] = ccol[(2 * stn) * cur_pitch + k];
-#pragma unroll
-                        for (int j = 0; j < KY; ++j) {
-                            uint32_t seg[SEGV * 4];
-#pragma unroll
-                            for (int v = 0; v < SEGV; ++v) {
-                                const uint4 t4 = ring[(u + j) % KY][v];
-                                seg[4 * v + 0] = t4.x;
-                                seg[4 * v + 1] = t4.y;
-                                seg[4 * v + 2] = t4.z;
-                                seg[4 * v + 3] = t4.w;
-                            }
-#pragma unroll
-                            for (int k = 0; k < CW; ++k)
-#pragma unroll
-                                for (int i = 0; i < KX; ++i)
-                                    acc[j][i] = __builtin_amdgcn_sad_u16(c[k], seg[k + i], acc[j][i]);
-                        }
-#pragma unroll
-                        for (int k = 0; k < CW; ++k) c[k] = cn[k];
+                        if (u & 1) one(u, st, cB, cA);
+                        else one(u, st, cA, cB);
                     }
                 }
             }
