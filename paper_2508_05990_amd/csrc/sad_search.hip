@@ -910,20 +910,24 @@ TileCfg default_tiles(int B, int R)
 {
     TileCfg c{};
     c.kx = 4;
-    // 4x4 tiles when the block is at least 16 wide and its main tiles give every
-    // wave of the block a full 64-lane task; otherwise 4x2 (more, shorter tasks
-    // and fewer registers: on 8-wide blocks, or radius 16 where 4x4 tiles make a
-    // single task for the block's four waves, 4x2 was faster in every measured
-    // frame size)
     const int n = 2 * R + 1;
-    c.ky = (B >= 16 && (n / 4) * (n / 4) >= 64 * kWavesPerBlock) ? 4 : 2;
-    // two blocks per workgroup share one window when the radius keeps their
-    // window starts 16-byte aligned (R % 4 == 0) and the window fits in a
-    // single band within 80 KB
+    // Two blocks per workgroup share one window when the radius keeps their
+    // window starts 16-byte aligned (R % 4 == 0), within 80 KB (two workgroups
+    // per CU).  4x4 tiles only where the block is at least 16 wide, its main
+    // tiles give every wave of the block a full 64-lane task and the whole
+    // window fits one band; otherwise 4x2 tiles (more, shorter tasks, fewer
+    // registers; banded windows at radius 64), which were faster on every
+    // other measured (block, radius, frame size).
     if (R % 4 == 0) {
         c.nb = 2;
-        if (plan_tiles(B, R, kLdsMid, &c) && c.band_ty * c.ky >= 2 * R + 1) return c;
+        if (B >= 16 && (n / 4) * (n / 4) >= 64 * kWavesPerBlock) {
+            c.ky = 4;
+            if (plan_tiles(B, R, kLdsMid, &c) && c.band_ty * c.ky >= n) return c;
+        }
+        c.ky = 2;
+        if (plan_tiles(B, R, kLdsMid, &c)) return c;
     }
+    c.ky = (B >= 16 && (n / 4) * (n / 4) >= 64 * kWavesPerBlock) ? 4 : 2;
     c.nb = 1;
     if (plan_tiles(B, R, kLdsCap, &c) || plan_tiles(B, R, kLdsMid, &c) || plan_tiles(B, R, kLdsMax, &c)) return c;
     return c;
