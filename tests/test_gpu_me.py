@@ -171,3 +171,35 @@ def test_uhd_sampled_blocks_bit_exact(dev, oracle_mod):
         mv_g, sad_g = _gpu_full(dev, seq.frames[t - 1], seq.frames[t], 16, 64)
         mv_o, sad_o, _ = oracle_mod.full_search(seq.frames[t - 1], seq.frames[t], 16, 64, blocks=idx)
         _assert_same(mv_g, sad_g, mv_o, sad_o, blocks=idx)
+
+
+@pytest.mark.parametrize("B", [8, 32, 64])
+@pytest.mark.parametrize("R", [48, 64])
+def test_large_radius_banded_pairs_bit_exact(dev, oracle_mod, B, R):
+    """Radius 48 and 64 with the default launch shape, the window staged in
+    several dy bands: blocks of 8 and 32 two per workgroup with 4x2 tiles
+    within 80 KB (32: rows walked in 16-word chunks); blocks of 64, whose two-
+    block window does not fit 80 KB, one per workgroup with 4x4 tiles; uniform
+    12-bit frames and a low-entropy pair full of ties."""
+    ctx = dev.Context(0)
+    try:
+        shape, tuned = dev.tuned_shape(ctx, B, R, 256, 384)
+        assert not tuned, shape
+        if B == 64:
+            assert shape[:3] == (4, 4, 1), shape
+        else:
+            assert shape[:3] == (4, 2, 2) and shape[3] <= 80, shape
+    finally:
+        ctx.close()
+    rng = np.random.default_rng(B * 1000 + R)
+    for trial in range(2):
+        if trial:
+            f0 = rng.integers(0, 3, size=(256, 384)).astype(np.uint16)
+            f1 = rng.integers(0, 3, size=(256, 384)).astype(np.uint16)
+        else:
+            f0 = rng.integers(0, 4096, size=(256, 384)).astype(np.uint16)
+            f1 = rng.integers(0, 4096, size=(256, 384)).astype(np.uint16)
+        print("banded B=%d R=%d trial %d" % (B, R, trial), flush=True)
+        mv_g, sad_g = _gpu_full(dev, f0, f1, B, R)
+        mv_o, sad_o, _ = oracle_mod.full_search(f0, f1, B, R)
+        _assert_same(mv_g, sad_g, mv_o, sad_o)
