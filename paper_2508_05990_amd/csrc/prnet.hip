@@ -683,19 +683,40 @@ __global__ __launch_bounds__(256) void ir_block_kernel(IrArgs a)
     constexpr int c4n = CH >> 2;
     const uint2* hin = reinterpret_cast<const uint2*>(a.h_in) + (size_t)img * a.Hf * a.Wf * c4n;
 
-    // every global read but the packed weights happens here, once
-    for (int e = threadIdx.x; e < kIrRows * c4n; e += blockDim.x) {
-        const int hp = e / c4n, c4 = e - hp * c4n;
-        uint2 v = make_uint2(0u, 0u);
-        if (hp < kIrHalo) {
-            const int gy = y0 + hp / kIrHW - 1, gx = x0 + hp % kIrHW - 1;
-            if (gy >= 0 && gy < a.Hf && gx >= 0 && gx < a.Wf) v = hin[((size_t)gy * a.Wf + gx) * c4n + c4];
+    // every global read but the packed weights happens here, once; a thread issues
+    // all of its halo loads (and groups of its parameter loads) before writing
+    // LDS, so their latencies overlap (256 threads, as launched)
+    {
+        constexpr int kH = (kIrRows * c4n + 255) / 256;
+        uint2 hv[kH];
+#pragma unroll
+        for (int u = 0; u < kH; ++u) {
+            const int e = threadIdx.x + 256 * u, hp = e / c4n, c4 = e - hp * c4n;
+            hv[u] = make_uint2(0u, 0u);
+            if (hp < kIrHalo) {
+                const int gy = y0 + hp / kIrHW - 1, gx = x0 + hp % kIrHW - 1;
+                if (gy >= 0 && gy < a.Hf && gx >= 0 && gx < a.Wf) hv[u] = hin[((size_t)gy * a.Wf + gx) * c4n + c4];
+            }
         }
-        *reinterpret_cast<uint2*>(hl + hp * ldh + 4 * c4) = v;
+#pragma unroll
+        for (int u = 0; u < kH; ++u) {
+            const int e = threadIdx.x + 256 * u, hp = e / c4n, c4 = e - hp * c4n;
+            if (hp < kIrRows) *reinterpret_cast<uint2*>(hl + hp * ldh + 4 * c4) = hv[u];
+        }
     }
-    for (int e = threadIdx.x; e < X * 11; e += blockDim.x) {
-        const int ch = e / 11, t = e - ch * 11;
-        wl[t < 10 ? ch * 10 + t : X * 10 + ch] = t < 9 ? a.wd[ch * 9 + t] : (t == 9 ? a.bd[ch] : a.be[ch]);
+    for (int e0 = threadIdx.x; e0 < X * 11; e0 += 4 * 256) {
+        float pv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + 256 * u, ch = e / 11, t = e - ch * 11;
+            pv[u] = 0.f;
+            if (e < X * 11) pv[u] = t < 9 ? a.wd[ch * 9 + t] : (t == 9 ? a.bd[ch] : a.be[ch]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + 256 * u, ch = e / 11, t = e - ch * 11;
+            if (e < X * 11) wl[t < 10 ? ch * 10 + t : X * 10 + ch] = pv[u];
+        }
     }
 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, n = lane & 15;
