@@ -663,12 +663,16 @@ __global__ __launch_bounds__(256) void reduce_rows_kernel(const float* __restric
 // depthwise-filter it into v (64 x 64), and fold v into the compression
 // accumulators, which stay in registers across chunks.  Rounding points match
 // the layer-by-layer path (u, v and h_out are bfloat16).  About 44 KB of LDS
-// per workgroup at 64 hidden channels, so three workgroups share a CU.
+// per workgroup at 64 hidden channels.
 constexpr int kIrT = 8, kIrHW = kIrT + 2, kIrHalo = kIrHW * kIrHW, kIrRows = 112;
 constexpr int kIrChunk = 64, kIrLd = kIrChunk + 8;
+// Eight waves: wave w takes the 16-channel row tile w % 4 of each product and
+// the pixel column tiles of half w / 4 (expansion: halo column tiles 0-3 or
+// 4-6; compression: output column tiles 0-1 or 2-3).
+constexpr int kIrThreads = 512;
 
 template <int CH>
-__global__ __launch_bounds__(256) void ir_block_kernel(IrArgs a)
+__global__ __launch_bounds__(kIrThreads) void ir_block_kernel(IrArgs a)
 {
     extern __shared__ __align__(16) uint16_t lds[];
     const int X = a.x;
@@ -685,13 +689,13 @@ __global__ __launch_bounds__(256) void ir_block_kernel(IrArgs a)
 
     // every global read but the packed weights happens here, once; a thread issues
     // all of its halo loads (and groups of its parameter loads) before writing
-    // LDS, so their latencies overlap (256 threads, as launched)
+    // LDS, so their latencies overlap (kIrThreads threads, as launched)
     {
-        constexpr int kH = (kIrRows * c4n + 255) / 256;
+        constexpr int kH = (kIrRows * c4n + kIrThreads - 1) / kIrThreads;
         uint2 hv[kH];
 #pragma unroll
         for (int u = 0; u < kH; ++u) {
-            const int e = threadIdx.x + 256 * u, hp = e / c4n, c4 = e - hp * c4n;
+            const int e = threadIdx.x + kIrThreads * u, hp = e / c4n, c4 = e - hp * c4n;
             hv[u] = make_uint2(0u, 0u);
             if (hp < kIrHalo) {
                 const int gy = y0 + hp / kIrHW - 1, gx = x0 + hp % kIrHW - 1;
@@ -700,39 +704,40 @@ __global__ __launch_bounds__(256) void ir_block_kernel(IrArgs a)
         }
 #pragma unroll
         for (int u = 0; u < kH; ++u) {
-            const int e = threadIdx.x + 256 * u, hp = e / c4n, c4 = e - hp * c4n;
+            const int e = threadIdx.x + kIrThreads * u, hp = e / c4n, c4 = e - hp * c4n;
             if (hp < kIrRows) *reinterpret_cast<uint2*>(hl + hp * ldh + 4 * c4) = hv[u];
         }
     }
-    for (int e0 = threadIdx.x; e0 < X * 11; e0 += 4 * 256) {
+    for (int e0 = threadIdx.x; e0 < X * 11; e0 += 4 * kIrThreads) {
         float pv[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int e = e0 + 256 * u, ch = e / 11, t = e - ch * 11;
+            const int e = e0 + kIrThreads * u, ch = e / 11, t = e - ch * 11;
             pv[u] = 0.f;
             if (e < X * 11) pv[u] = t < 9 ? a.wd[ch * 9 + t] : (t == 9 ? a.bd[ch] : a.be[ch]);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int e = e0 + 256 * u, ch = e / 11, t = e - ch * 11;
+            const int e = e0 + kIrThreads * u, ch = e / 11, t = e - ch * 11;
             if (e < X * 11) wl[t < 10 ? ch * 10 + t : X * 10 + ch] = pv[u];
         }
     }
 
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, n = lane & 15;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, n = lane & 15;
+    const int w = wv & 3, half = wv >> 2;                  // row-tile role, column half
     const uint2* we = reinterpret_cast<const uint2*>(a.we);
     const uint2* wc = reinterpret_cast<const uint2*>(a.wc);
     constexpr int KSe = CH >> 4, MTc = CH >> 4, MPW = (MTc + 3) / 4;   // compression row tiles per wave
     const int KSc = X >> 4, nq = X / kIrChunk;
-    // Wave w owns expansion row tile w of every chunk (16 of its 64 channels)
-    // and compression row tiles w, w + 4, ...: it loads only those weights and
-    // reuses them across all column (pixel) tiles; the next chunk's weights are
-    // loaded while the current chunk is computed.
-    v4f32 acc2[MPW][4];
+    // Role w owns expansion row tile w of every chunk (16 of its 64 channels)
+    // and compression row tiles w, w + 4, ...: its two waves load only those
+    // weights and reuse them across their half's column (pixel) tiles; the next
+    // chunk's weights are loaded while the current chunk is computed.
+    v4f32 acc2[MPW][2];
 #pragma unroll
     for (int j = 0; j < MPW; ++j)
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) acc2[j][nt] = (v4f32){0.f, 0.f, 0.f, 0.f};
+        for (int nt = 0; nt < 2; ++nt) acc2[j][nt] = (v4f32){0.f, 0.f, 0.f, 0.f};
     const int c4 = threadIdx.x & 15;                       // channel group of this thread in the depthwise step
     v4i16 wa[KSe], wb[MPW][4];
 #pragma unroll
@@ -762,7 +767,9 @@ __global__ __launch_bounds__(256) void ir_block_kernel(IrArgs a)
         const float* bexp = wl + X * 10 + q * kIrChunk + oe;
         const float be0 = bexp[0], be1 = bexp[1], be2 = bexp[2], be3 = bexp[3];
 #pragma unroll
-        for (int nt = 0; nt < kIrRows / 16; ++nt) {
+        for (int ntl = 0; ntl < 4; ++ntl) {
+            const int nt = 4 * half + ntl;
+            if (nt >= kIrRows / 16) break;
             const int hp = nt * 16 + n;
             const int gy = y0 + hp / kIrHW - 1, gx = x0 + hp % kIrHW - 1;
             const bool inside = hp < kIrHalo && gy >= 0 && gy < a.Hf && gx >= 0 && gx < a.Wf;
@@ -775,13 +782,13 @@ __global__ __launch_bounds__(256) void ir_block_kernel(IrArgs a)
                        : make_uint2(0u, 0u);
         }
         __syncthreads();
-        // depthwise: 64 pixels x 16 channel groups, 4 per thread
+        // depthwise: 64 pixels x 16 channel groups, 2 per thread
         float wk[40];
 #pragma unroll
         for (int i = 0; i < 40; ++i) wk[i] = wl[(q * kIrChunk + 4 * c4) * 10 + i];
-#pragma unroll 2
-        for (int j = 0; j < 4; ++j) {
-            const int px = (threadIdx.x >> 4) + 16 * j, ty = px >> 3, tx = px & 7;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int px = (threadIdx.x >> 4) + 32 * j, ty = px >> 3, tx = px & 7;
             float acc[4] = {wk[9], wk[19], wk[29], wk[39]};
 #pragma unroll
             for (int ky = 0; ky < 3; ++ky)
@@ -799,15 +806,15 @@ __global__ __launch_bounds__(256) void ir_block_kernel(IrArgs a)
                 pack4(relu6f(acc[0]), relu6f(acc[1]), relu6f(acc[2]), relu6f(acc[3]));
         }
         __syncthreads();
-        // compression: row tiles w + 4 j over the four column tiles (64 pixels)
+        // compression: row tiles w + 4 j over this half's two column tiles (32 pixels)
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            const uint16_t* brow = vl + (nt * 16 + n) * kIrLd + 4 * g;
+        for (int ntl = 0; ntl < 2; ++ntl) {
+            const uint16_t* brow = vl + ((2 * half + ntl) * 16 + n) * kIrLd + 4 * g;
 #pragma unroll
             for (int ks = 0; ks < kIrChunk / 16; ++ks) {
                 const v4i16 b = as_v4(*reinterpret_cast<const uint2*>(brow + ks * 16));
 #pragma unroll
-                for (int j = 0; j < MPW; ++j) acc2[j][nt] = mfma(wb[j][ks], b, acc2[j][nt]);
+                for (int j = 0; j < MPW; ++j) acc2[j][ntl] = mfma(wb[j][ks], b, acc2[j][ntl]);
             }
         }
 #pragma unroll
@@ -827,13 +834,13 @@ __global__ __launch_bounds__(256) void ir_block_kernel(IrArgs a)
         const int o = t * 16 + 4 * g;
         const float bc0 = a.bc[o], bc1 = a.bc[o + 1], bc2 = a.bc[o + 2], bc3 = a.bc[o + 3];
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            const int px = nt * 16 + n, ty = px >> 3, tx = px & 7, gy = y0 + ty, gx = x0 + tx;
+        for (int ntl = 0; ntl < 2; ++ntl) {
+            const int px = (2 * half + ntl) * 16 + n, ty = px >> 3, tx = px & 7, gy = y0 + ty, gx = x0 + tx;
             if (gy >= a.Hf || gx >= a.Wf) continue;
             const float4 sk = unpack4(*reinterpret_cast<const uint2*>(hl + ((ty + 1) * kIrHW + tx + 1) * ldh + o));
             hout[((size_t)gy * a.Wf + gx) * c4n + (o >> 2)] =
-                pack4(acc2[j][nt][0] + bc0 + sk.x, acc2[j][nt][1] + bc1 + sk.y, acc2[j][nt][2] + bc2 + sk.z,
-                      acc2[j][nt][3] + bc3 + sk.w);
+                pack4(acc2[j][ntl][0] + bc0 + sk.x, acc2[j][ntl][1] + bc1 + sk.y, acc2[j][ntl][2] + bc2 + sk.z,
+                      acc2[j][ntl][3] + bc3 + sk.w);
         }
     }
 }
@@ -1305,12 +1312,12 @@ hipError_t launch_ir_block(const IrArgs& a, hipStream_t st)
     if (!ir_fused_ok(a.ch, a.x)) return hipErrorInvalidValue;
     const size_t lds = ir_lds_bytes(a.ch, a.x);
     switch (a.ch) {
-    case 16: hipLaunchKernelGGL(ir_block_kernel<16>, dim3(tiles), dim3(256), lds, st, a); break;
-    case 32: hipLaunchKernelGGL(ir_block_kernel<32>, dim3(tiles), dim3(256), lds, st, a); break;
-    case 48: hipLaunchKernelGGL(ir_block_kernel<48>, dim3(tiles), dim3(256), lds, st, a); break;
-    case 64: hipLaunchKernelGGL(ir_block_kernel<64>, dim3(tiles), dim3(256), lds, st, a); break;
-    case 96: hipLaunchKernelGGL(ir_block_kernel<96>, dim3(tiles), dim3(256), lds, st, a); break;
-    case 128: hipLaunchKernelGGL(ir_block_kernel<128>, dim3(tiles), dim3(256), lds, st, a); break;
+    case 16: hipLaunchKernelGGL(ir_block_kernel<16>, dim3(tiles), dim3(kIrThreads), lds, st, a); break;
+    case 32: hipLaunchKernelGGL(ir_block_kernel<32>, dim3(tiles), dim3(kIrThreads), lds, st, a); break;
+    case 48: hipLaunchKernelGGL(ir_block_kernel<48>, dim3(tiles), dim3(kIrThreads), lds, st, a); break;
+    case 64: hipLaunchKernelGGL(ir_block_kernel<64>, dim3(tiles), dim3(kIrThreads), lds, st, a); break;
+    case 96: hipLaunchKernelGGL(ir_block_kernel<96>, dim3(tiles), dim3(kIrThreads), lds, st, a); break;
+    case 128: hipLaunchKernelGGL(ir_block_kernel<128>, dim3(tiles), dim3(kIrThreads), lds, st, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
