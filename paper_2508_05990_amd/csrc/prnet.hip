@@ -855,8 +855,9 @@ __global__ __launch_bounds__(kIrThreads) void ir_block_kernel(IrArgs a)
 // values the layer-by-layer path stores; zero outside the image, the zero
 // padding of the next depthwise layer); the last 1x1 runs on MFMA.
 constexpr int kEncT = 8, kEncE2 = 2 * kEncT + 1, kEncA0 = 2 * kEncE2 + 1;
+constexpr int kEncThreads = 512;   // eight waves
 
-__global__ __launch_bounds__(256) void encoder_kernel(EncArgs a)
+__global__ __launch_bounds__(kEncThreads) void encoder_kernel(EncArgs a)
 {
     extern __shared__ __align__(16) float fl[];
     const int CE = a.ce;
@@ -890,19 +891,39 @@ __global__ __launch_bounds__(256) void encoder_kernel(EncArgs a)
         else v = a.b3[e - 40 - CE * 15];
         wv[e] = v;
     }
-    // packed planes (v - 2048) / 1024 on 35 x 35 positions from packed (4 Y0 - 3, 4 X0 - 3)
+    // packed planes (v - 2048) / 1024 on 35 x 35 positions from packed (4 Y0 - 3, 4 X0 - 3);
+    // a thread issues all of its mosaic loads before converting and writing LDS
     const uint16_t* m = a.mosaic + img * a.img_stride;
-    for (int e = tid; e < kEncA0 * kEncA0; e += nt) {
-        const int r = e / kEncA0, c = e - r * kEncA0;
-        const int py = 4 * Y0 - 3 + r, px = 4 * X0 - 3 + c;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (py >= 0 && py < a.Hp && px >= 0 && px < a.Wp) {
-            const uint16_t* q = m + (int64_t)(2 * py) * a.pitch + 2 * px;
-            const float k = 1.f / 1024.f;
-            v = unpack4(pack4(((float)q[0] - 2048.f) * k, ((float)q[1] - 2048.f) * k, ((float)q[a.pitch] - 2048.f) * k,
-                              ((float)q[a.pitch + 1] - 2048.f) * k));
+    {
+        constexpr int kPl = (kEncA0 * kEncA0 + kEncThreads - 1) / kEncThreads;
+        uint16_t qv[kPl][4];
+        bool in[kPl];
+#pragma unroll
+        for (int u = 0; u < kPl; ++u) {
+            const int e = tid + kEncThreads * u, r = e / kEncA0, c = e - r * kEncA0;
+            const int py = 4 * Y0 - 3 + r, px = 4 * X0 - 3 + c;
+            in[u] = e < kEncA0 * kEncA0 && py >= 0 && py < a.Hp && px >= 0 && px < a.Wp;
+            qv[u][0] = qv[u][1] = qv[u][2] = qv[u][3] = 0;
+            if (in[u]) {
+                const uint16_t* q = m + (int64_t)(2 * py) * a.pitch + 2 * px;
+                qv[u][0] = q[0];
+                qv[u][1] = q[1];
+                qv[u][2] = q[a.pitch];
+                qv[u][3] = q[a.pitch + 1];
+            }
         }
-        *reinterpret_cast<float4*>(a0 + 4 * e) = v;
+#pragma unroll
+        for (int u = 0; u < kPl; ++u) {
+            const int e = tid + kEncThreads * u;
+            if (e >= kEncA0 * kEncA0) break;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (in[u]) {
+                const float k = 1.f / 1024.f;
+                v = unpack4(pack4(((float)qv[u][0] - 2048.f) * k, ((float)qv[u][1] - 2048.f) * k,
+                                  ((float)qv[u][2] - 2048.f) * k, ((float)qv[u][3] - 2048.f) * k));
+            }
+            *reinterpret_cast<float4*>(a0 + 4 * e) = v;
+        }
     }
     __syncthreads();
     // e1: depthwise stride 2 of the planes on 17 x 17 positions from (2 Y0 - 1, 2 X0 - 1)
@@ -955,15 +976,17 @@ __global__ __launch_bounds__(256) void encoder_kernel(EncArgs a)
     }
     for (int e = tid; e < kEncT * kEncT * 8; e += nt) e3[(e >> 3) * ldc + CE + (e & 7)] = 0;
     __syncthreads();
-    // e4: 1x1 CE -> CE on MFMA; wave w takes pixels 16 w .. 16 w + 15
+    // e4: 1x1 CE -> CE on MFMA; wave w takes pixels 16 (w % 4) .. + 15 and the
+    // 16-channel output row tiles w / 4, w / 4 + 2, ...
     const int lane = tid & 63, w = tid >> 6, g = lane >> 4, n = lane & 15;
     const int KS = (CE + 15) >> 4, MT = (CE + 15) >> 4;
     const uint2* wp = reinterpret_cast<const uint2*>(a.w3p);
-    const uint16_t* brow = e3 + (16 * w + n) * ldc + 4 * g;
-    const int px = 16 * w + n, Y = Y0 + (px >> 3), X = X0 + (px & 7);
+    const int pg = w & 3, nw = (nt >> 6) >> 2;             // pixel group, waves per pixel group
+    const uint16_t* brow = e3 + (16 * pg + n) * ldc + 4 * g;
+    const int px = 16 * pg + n, Y = Y0 + (px >> 3), X = X0 + (px & 7);
     const bool inside = Y < a.Hf && X < a.Wf;
     uint2* out = reinterpret_cast<uint2*>(a.out) + ((size_t)img * a.Hf * a.Wf + (size_t)Y * a.Wf + X) * (CE >> 2);
-    for (int t = 0; t < MT; ++t) {
+    for (int t = w >> 2; t < MT; t += nw) {
         v4f32 acc = (v4f32){0.f, 0.f, 0.f, 0.f};
         for (int ks = 0; ks < KS; ++ks)
             acc = mfma(as_v4(wp[((size_t)t * KS + ks) * 64 + lane]), as_v4(*reinterpret_cast<const uint2*>(brow + 16 * ks)),
@@ -1339,7 +1362,7 @@ hipError_t launch_encoder(const EncArgs& a, hipStream_t st)
     const size_t lds = enc_lds_bytes(a.ce);
     hipError_t e = allow_lds(reinterpret_cast<const void*>(encoder_kernel), lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(encoder_kernel, dim3(tiles), dim3(256), lds, st, a);
+    hipLaunchKernelGGL(encoder_kernel, dim3(tiles), dim3(kEncThreads), lds, st, a);
     return hipGetLastError();
 }
 
