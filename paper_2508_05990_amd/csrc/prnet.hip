@@ -176,7 +176,8 @@ __device__ void stage_cols(const PwTensor& t, int koff, int p0, int p1, int HW, 
 
 // ------------------------------------------------------------ 1x1 GEMM --
 
-constexpr int kScLd = kPx + 4;   // row length (floats) of a wave's transpose slice
+// Row length (floats) of a wave's transpose slice: NCT 16-pixel column tiles.
+__host__ __device__ constexpr int pw_scld(int nct) { return 16 * nct + 4; }
 
 // Channels-first output through the per-wave LDS transpose: four-pixel groups
 // never straddle two images when HW is a multiple of 4.
@@ -185,22 +186,27 @@ __host__ __device__ inline bool pw_chw_fast(const PwArgs& a)
     return a.out_chw && (a.HW & 3) == 0 && !a.mask && (!a.add.p || a.add.chw);
 }
 
-// One workgroup per 64-pixel tile (grid-stride over tiles).  Wave w owns the
-// output row tiles w, w + 4, ... (16 channels each) for all four 16-pixel
-// column tiles of the tile: it loads each A operand (packed weights) once and
-// applies it to the four column tiles read from LDS.
-__global__ __launch_bounds__(256) void pw_kernel(PwArgs a)
+// One workgroup of NW waves per 64-pixel tile (grid-stride over tiles).  Wave
+// w owns the output row tiles w % 4, w % 4 + 4, ... (16 channels each) for the
+// NCT = 16 / NW column tiles (16 pixels each) of part w / 4 of the tile: it
+// loads each A operand (packed weights) once and applies it to its column
+// tiles read from LDS.  Eight waves halve each wave's chain for grids of about
+// one round; four keep more workgroups per CU on larger grids.
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void pw_kernel(PwArgs a)
 {
     extern __shared__ __align__(16) uint16_t lds[];
     const int K = a.KS * 16, ldk = K + 4;   // rows 8-byte aligned, 18 mod 64 banks apart
     const int MT = (a.M + 15) >> 4;
     uint16_t* xl = lds;
     const uint2* wp = reinterpret_cast<const uint2*>(a.w);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, n = lane & 15;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, n = lane & 15;
+    constexpr int NCT = 16 / NW, kScLd = pw_scld(NCT);
+    const int w = wv & 3, half = wv >> 2;                  // row-tile role, column part
     const int ntiles = (a.P + kPx - 1) / kPx;
     const int kc = a.x.C + (a.x2.p ? a.x2.C : 0);
     const bool chw_fast = pw_chw_fast(a);
-    float* sc = reinterpret_cast<float*>(xl + kPx * ldk) + w * 16 * kScLd;
+    float* sc = reinterpret_cast<float*>(xl + kPx * ldk) + wv * 16 * kScLd;
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int p0 = tile * kPx;
         __syncthreads();                                   // the previous tile's reads of xl are done
@@ -213,14 +219,15 @@ __global__ __launch_bounds__(256) void pw_kernel(PwArgs a)
         __syncthreads();
 
         for (int t = w; t < MT; t += 4) {
-            v4f32 acc[4];
+            v4f32 acc[NCT];
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) acc[nt] = (v4f32){0.f, 0.f, 0.f, 0.f};
+            for (int nt = 0; nt < NCT; ++nt) acc[nt] = (v4f32){0.f, 0.f, 0.f, 0.f};
             for (int ks = 0; ks < a.KS; ++ks) {
                 const v4i16 wa = as_v4(wp[((size_t)t * a.KS + ks) * 64 + lane]);
 #pragma unroll
-                for (int nt = 0; nt < 4; ++nt)
-                    acc[nt] = mfma(wa, as_v4(*reinterpret_cast<const uint2*>(xl + (nt * 16 + n) * ldk + ks * 16 + 4 * g)),
+                for (int nt = 0; nt < NCT; ++nt)
+                    acc[nt] = mfma(wa,
+                                   as_v4(*reinterpret_cast<const uint2*>(xl + ((NCT * half + nt) * 16 + n) * ldk + ks * 16 + 4 * g)),
                                    acc[nt]);
             }
             const int o = t * 16 + 4 * g;
@@ -230,10 +237,10 @@ __global__ __launch_bounds__(256) void pw_kernel(PwArgs a)
                 for (int i = 0; i < 4; ++i) bias[i] = a.bias[o + i];
             }
             if (chw_fast) {
-                // channels-first output: transpose the 16 x 64 tile through this wave's LDS
+                // channels-first output: transpose the wave's 16 x 16 NCT tile through its LDS
                 // slice so that each lane reads/writes four consecutive pixels of one channel
 #pragma unroll
-                for (int nt = 0; nt < 4; ++nt)
+                for (int nt = 0; nt < NCT; ++nt)
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const float v = acc[nt][i] + bias[i];
@@ -243,9 +250,9 @@ __global__ __launch_bounds__(256) void pw_kernel(PwArgs a)
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int idx = lane + 64 * r, ch = idx >> 4, q4 = idx & 15;
-                    const int oc = t * 16 + ch, px = p0 + 4 * q4;
+                for (int r = 0; r < NCT; ++r) {
+                    const int idx = lane + 64 * r, ch = idx / (4 * NCT), q4 = idx % (4 * NCT);
+                    const int oc = t * 16 + ch, px = p0 + 16 * NCT * half + 4 * q4;
                     if (oc >= a.M || px >= a.P) continue;
                     float4 v = *reinterpret_cast<const float4*>(sc + ch * kScLd + 4 * q4);
                     const int img = px / a.HW, hw = px - img * a.HW;
@@ -268,8 +275,8 @@ __global__ __launch_bounds__(256) void pw_kernel(PwArgs a)
             }
             if (o >= a.M) continue;
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                const int p = p0 + nt * 16 + n;
+            for (int nt = 0; nt < NCT; ++nt) {
+                const int p = p0 + (NCT * half + nt) * 16 + n;
                 if (p >= a.P) continue;
                 float v[4];
 #pragma unroll
@@ -1206,10 +1213,19 @@ hipError_t launch_pw(const PwArgs& a, hipStream_t st)
 {
     if (a.P <= 0) return hipSuccess;
     const int ntiles = div_up(a.P, kPx);
-    const size_t lds = pw_lds_bytes(a.KS) + (pw_chw_fast(a) ? 4 * 16 * kScLd * sizeof(float) : 0);
-    hipError_t e = allow_lds(reinterpret_cast<const void*>(pw_kernel), lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(pw_kernel, dim3(ntiles < 2048 ? ntiles : 2048), dim3(256), lds, st, a);
+    const dim3 grid(ntiles < 2048 ? ntiles : 2048);
+    // eight waves while the tiles fit in about one round of workgroups, four beyond
+    if (ntiles <= 1024) {
+        const size_t lds = pw_lds_bytes(a.KS) + (pw_chw_fast(a) ? 8 * 16 * pw_scld(2) * sizeof(float) : 0);
+        hipError_t e = allow_lds(reinterpret_cast<const void*>(pw_kernel<8>), lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(pw_kernel<8>, grid, dim3(512), lds, st, a);
+    } else {
+        const size_t lds = pw_lds_bytes(a.KS) + (pw_chw_fast(a) ? 4 * 16 * pw_scld(4) * sizeof(float) : 0);
+        hipError_t e = allow_lds(reinterpret_cast<const void*>(pw_kernel<4>), lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(pw_kernel<4>, grid, dim3(256), lds, st, a);
+    }
     return hipGetLastError();
 }
 

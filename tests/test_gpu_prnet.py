@@ -116,8 +116,10 @@ def _pw_ref(x, W, b, relu6, add, mask):
     return y, absterm
 
 
+# up to 1024 pixel tiles the kernel runs eight waves per workgroup, beyond four
+# (2 x 33000 pixels: 1032 tiles)
 @pytest.mark.parametrize("n,HW,cin,cout", [(2, 100, 4, 32), (1, 317, 64, 256), (3, 64, 16, 16), (2, 211, 256, 64),
-                                           (1, 70, 32, 48)])
+                                           (1, 70, 32, 48), (2, 33000, 64, 64)])
 def test_pw_forward_nhwc(dev, ctx, n, HW, cin, cout):
     import torch
 
@@ -141,11 +143,13 @@ def test_pw_forward_nhwc(dev, ctx, n, HW, cin, cout):
             _close(got, ref, absterm, (relu6, use_add, use_mask))
 
 
-@pytest.mark.parametrize("zdtype,Hf,Wf", [("f32", 9, 23), ("bf16", 9, 23), ("f32", 8, 23), ("bf16", 12, 5)])
+@pytest.mark.parametrize("zdtype,Hf,Wf", [("f32", 9, 23), ("bf16", 9, 23), ("f32", 8, 23), ("bf16", 12, 5),
+                                          ("f32", 136, 244), ("bf16", 137, 243)])
 def test_pw_forward_concat_and_channels_first(dev, ctx, zdtype, Hf, Wf):
     """The projection's input [z_pred (channels-first), encoder (channels-last)]
     and the head's channels-first output with z_pred added (pixels per image a
-    multiple of 4 or not: two store paths)."""
+    multiple of 4 or not: two store paths; the last two shapes have more than
+    1024 pixel tiles)."""
     import torch
 
     rng = np.random.default_rng(5)
