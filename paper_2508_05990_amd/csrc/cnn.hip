@@ -174,6 +174,80 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const uint16_t* __restric
     }
 }
 
+// Split-k variant for small grids: a workgroup's four waves take the same 16
+// output pixels and the k-steps w, w + 4, ... each; the partial sums meet in
+// LDS and wave 0 adds them in wave order (a fixed order: results stay
+// reproducible), then stores as conv_fwd_kernel does.  Four times the waves and
+// a quarter of each wave's chain of dependent products.
+template <int CIN, int COUT, int S, bool LAST>
+__global__ __launch_bounds__(256) void conv_fwd_split_kernel(const uint16_t* __restrict__ in,
+                                                             const uint16_t* __restrict__ wp,
+                                                             const float* __restrict__ bias, void* __restrict__ out,
+                                                             int n, int H, int W, int Ho, int Wo)
+{
+    constexpr int K = 9 * CIN, KS = (K + 15) / 16, MT = (COUT + 15) / 16;
+    __shared__ v4f32 part[3][MT][64];
+    const int lane = threadIdx.x & 63, g = lane >> 4, w = threadIdx.x >> 6;
+    const int P = n * Ho * Wo;
+    const int p = blockIdx.x * 16 + (lane & 15);
+    const bool valid = p < P;
+    const int pp = valid ? p : 0;
+    const int img = pp / (Ho * Wo), rem = pp - img * Ho * Wo;
+    const int oy = rem / Wo, ox = rem - oy * Wo;
+    const uint16_t* src = in + (size_t)img * H * W * CIN;
+
+    v4f32 acc[MT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) acc[t] = (v4f32){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < (KS + 3) / 4; ++j) {
+        const int ks = 4 * j + w;
+        if (ks >= KS) break;
+        const int k0 = ks * 16 + 4 * g;
+        uint2 bv = make_uint2(0u, 0u);
+        if (k0 < K) {
+            const int tap = k0 / CIN, c = k0 - tap * CIN;
+            const int iy = oy * S + tap / 3 - 1, ix = ox * S + tap % 3 - 1;
+            if (iy >= 0 && iy < H && ix >= 0 && ix < W)
+                bv = *reinterpret_cast<const uint2*>(src + ((size_t)iy * W + ix) * CIN + c);
+        }
+        const v4i16 b = as_v4(bv);
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+            const uint2 av = reinterpret_cast<const uint2*>(wp)[(t * KS + ks) * 64 + lane];
+            acc[t] = mfma(as_v4(av), b, acc[t]);
+        }
+    }
+    if (w > 0) {
+#pragma unroll
+        for (int t = 0; t < MT; ++t) part[w - 1][t][lane] = acc[t];
+    }
+    __syncthreads();
+    if (w != 0 || !valid) return;
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+        acc[t] = acc[t] + part[0][t][lane];
+        acc[t] = acc[t] + part[1][t][lane];
+        acc[t] = acc[t] + part[2][t][lane];
+    }
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+        const int o0 = t * 16 + 4 * g;
+        float v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = acc[t][i] + (o0 + i < COUT ? bias[o0 + i] : 0.f);
+        if (LAST) {
+            float* o = reinterpret_cast<float*>(out) + (size_t)img * COUT * Ho * Wo + rem;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (o0 + i < COUT) o[(size_t)(o0 + i) * Ho * Wo] = v[i];
+        } else {
+            uint16_t* o = reinterpret_cast<uint16_t*>(out) + (size_t)pp * COUT + o0;
+            *reinterpret_cast<uint2*>(o) = pack4(fmaxf(v[0], 0.f), fmaxf(v[1], 0.f), fmaxf(v[2], 0.f), fmaxf(v[3], 0.f));
+        }
+    }
+}
+
 // ------------------------------------------------------------------ loss --
 
 __device__ __forceinline__ float berhu(float x, float c) { const float a = fabsf(x); return a <= c ? a : (x * x + c * c) / (2.f * c); }
@@ -445,6 +519,17 @@ hipError_t launch_conv_fwd(int l, const uint16_t* in, const uint16_t* wp, const 
 {
     const int P = n * Ho * Wo;
     dim3 grid(div_up(P, 64)), blk(256);
+    if (div_up(P, 64) < 1024) {   // small grid: split the k-steps over the workgroup's waves
+        const dim3 sg(div_up(P, 16));
+        switch (l) {
+        case 0: hipLaunchKernelGGL((conv_fwd_split_kernel<8, 32, 2, false>), sg, blk, 0, st, in, wp, bias, out, n, H, W, Ho, Wo); break;
+        case 1: hipLaunchKernelGGL((conv_fwd_split_kernel<32, 32, 2, false>), sg, blk, 0, st, in, wp, bias, out, n, H, W, Ho, Wo); break;
+        case 2: hipLaunchKernelGGL((conv_fwd_split_kernel<32, 32, 2, false>), sg, blk, 0, st, in, wp, bias, out, n, H, W, Ho, Wo); break;
+        case 3: hipLaunchKernelGGL((conv_fwd_split_kernel<32, 3, 1, true>), sg, blk, 0, st, in, wp, bias, out, n, H, W, Ho, Wo); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (l) {
     case 0: hipLaunchKernelGGL((conv_fwd_kernel<8, 32, 2, false>), grid, blk, 0, st, in, wp, bias, out, n, H, W, Ho, Wo); break;
     case 1: hipLaunchKernelGGL((conv_fwd_kernel<32, 32, 2, false>), grid, blk, 0, st, in, wp, bias, out, n, H, W, Ho, Wo); break;
