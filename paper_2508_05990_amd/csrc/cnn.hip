@@ -45,11 +45,27 @@ __global__ void pool_kernel(const uint16_t* __restrict__ ref, int64_t ref_pitch,
     for (int f = 0; f < 2; ++f) {
         const uint16_t* m = f ? cur : ref;
         const int64_t pitch = f ? cur_pitch : ref_pitch;
+        // the 4 x 4 mosaic samples of the cell: one 8-byte load per row when rows are 8-byte aligned
+        uint32_t q[4][4];
+        if ((pitch & 3) == 0 && (reinterpret_cast<uintptr_t>(m) & 7) == 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint2 u = *reinterpret_cast<const uint2*>(m + (4LL * y + r) * pitch + 4LL * x);
+                q[r][0] = u.x & 0xffffu;
+                q[r][1] = u.x >> 16;
+                q[r][2] = u.y & 0xffffu;
+                q[r][3] = u.y >> 16;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) q[r][k] = m[(4LL * y + r) * pitch + 4LL * x + k];
+        }
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            const int64_t r0 = 4LL * y + (c >> 1), c0 = 4LL * x + (c & 1);
-            const uint32_t s = (uint32_t)m[r0 * pitch + c0] + m[r0 * pitch + c0 + 2] + m[(r0 + 2) * pitch + c0] +
-                               m[(r0 + 2) * pitch + c0 + 2];
+            const int r0 = c >> 1, c0 = c & 1;
+            const uint32_t s = q[r0][c0] + q[r0][c0 + 2] + q[r0 + 2][c0] + q[r0 + 2][c0 + 2];
             v[4 * f + c] = ((float)s * 0.25f - 2048.0f) * (1.0f / 1024.0f);
         }
     }

@@ -75,6 +75,18 @@ def test_pool_bit_exact(dev, ctx, oracle_mod):
     torch.cuda.synchronize()
     ref = cnn.pool_input(oracle_mod.pack_planes(f0), oracle_mod.pack_planes(f1))
     assert np.array_equal(np.transpose(_np(x), (2, 0, 1)), ref)
+    # rows not 8-byte aligned (pitch of W + 2 samples; a view starting two samples in,
+    # 4-byte aligned as the ABI requires): the per-sample load path gives the same values
+    H, W = f0.shape
+    for off in (0, 2):
+        big0 = np.zeros((H, W + 2), np.uint16)
+        big1 = np.zeros((H, W + 2), np.uint16)
+        assert off + W <= W + 2
+        big0[:, off:off + W], big1[:, off:off + W] = f0, f1
+        t0, t1 = torch.from_numpy(big0).cuda(), torch.from_numpy(big1).cuda()
+        x = dev.cnn_pool(ctx, t0[:, off:off + W], t1[:, off:off + W])
+        torch.cuda.synchronize()
+        assert np.array_equal(np.transpose(_np(x), (2, 0, 1)), ref), off
 
 
 @pytest.mark.parametrize("layer", [0, 1, 2, 3])
