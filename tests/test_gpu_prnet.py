@@ -247,10 +247,11 @@ def _net_inputs(seed, n, H, W, cfg):
 
 # (32, 16, 16, 2, 2): expanded width 32, blocks layer by layer; the others have
 # expanded widths that are multiples of 64 and take the fused block kernel
-# (hidden widths 32, 16, 96 and 128).
+# (hidden widths 32, 16, 96, 128 and 48).
 @pytest.mark.parametrize("zdtype,cfgt,nimg", [("f32", CFG_SMALL, 2), ("bf16", CFG_SMALL, 2),
                                               ("f32", (32, 16, 32, 2, 2), 2), ("bf16", (48, 16, 16, 4, 1), 3),
-                                              ("f32", (64, 16, 96, 2, 1), 2), ("bf16", (32, 16, 128, 1, 1), 2)])
+                                              ("f32", (64, 16, 96, 2, 1), 2), ("bf16", (32, 16, 128, 1, 1), 2),
+                                              ("f32", (32, 16, 48, 4, 1), 2)])
 def test_network_forward(dev, ctx, zdtype, cfgt, nimg):
     import torch
 
