@@ -68,10 +68,11 @@ __global__ __launch_bounds__(256) void warp_kernel(const void* __restrict__ zin,
             if (cb + u >= c1) break;
             const float acc = warp_mix(tp, v[u][0], v[u][1], v[u][2], v[u][3]);
             const size_t o = (size_t)(cb + u) * plane + cell;
+            // the output is written once and not read back here: non-temporal stores
             if (BF16)
-                reinterpret_cast<uint16_t*>(zout)[o] = f2bf(acc);
+                __builtin_nontemporal_store(f2bf(acc), reinterpret_cast<uint16_t*>(zout) + o);
             else
-                reinterpret_cast<float*>(zout)[o] = acc;
+                __builtin_nontemporal_store(acc, reinterpret_cast<float*>(zout) + o);
         }
     }
 }
