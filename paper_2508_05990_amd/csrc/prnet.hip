@@ -265,8 +265,14 @@ __global__ __launch_bounds__(NW * 64) void pw_kernel(PwArgs a)
                         v.z += d.z;
                         v.w += d.w;
                     }
-                    if (a.out_f32) *reinterpret_cast<float4*>(static_cast<float*>(a.out) + gi) = v;
-                    else *reinterpret_cast<uint2*>(static_cast<uint16_t*>(a.out) + gi) = pack4(v.x, v.y, v.z, v.w);
+                    if (a.out_f32) {
+                        // a float32 channels-first output is the network's result: written once, so
+                        // non-temporal stores
+                        const v4f32 nv = {v.x, v.y, v.z, v.w};
+                        __builtin_nontemporal_store(nv, reinterpret_cast<v4f32*>(static_cast<float*>(a.out) + gi));
+                    } else {
+                        *reinterpret_cast<uint2*>(static_cast<uint16_t*>(a.out) + gi) = pack4(v.x, v.y, v.z, v.w);
+                    }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
