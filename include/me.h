@@ -300,29 +300,33 @@ me_status me_cnn_loss(me_ctx ctx, const float* out, const int16_t* mv, const flo
                       int32_t radius, int32_t refine_radius, uint16_t* dz, float* loss, void* stream);
 me_status me_cnn_adamw(me_ctx ctx, const float* grads, float lr, void* stream);
 
-/* One frame pair of a batch (me_batch_submit). */
+/* One frame pair of a batch (me_batch_submit).  params.mode must be
+ * ME_MODE_EXHAUSTIVE with step 1: a batch job has no fallback output and no
+ * network state, so pairs in learned-proposal mode go through me_estimate
+ * (ME_E_UNSUPPORTED otherwise). */
 typedef struct {
     me_frame ref;
     me_frame cur;
-    me_params params;      /* exhaustive mode only */
+    me_params params;      /* exhaustive mode, step 1 */
     int16_t* mv;           /* device [bh][bw][2] */
     int32_t* sad;          /* device [bh][bw] */
 } me_job;
 
 /*
  * me_batch_submit -- many independent frame pairs of mixed sizes, block sizes
- * and radii in one launch (the paper's batched grid over (Batch, h, w),
- * Sec. 4.1 CUDA settings, extended to uneven jobs).  jobs is a HOST array of
- * n entries (read before return); results are bit-identical to n separate
- * me_estimate calls.  The work is cut into items (a run of blocks of one
- * block row of one job), one workgroup each; jobs with equal LDS needs share
- * a launch, items ordered by decreasing cost.  The launches are captured as
- * one HIP graph and replayed while the job shapes repeat; each submission
- * stages its job table through pinned memory into context-owned device
- * tables (the item list too when the shapes change).  Submissions that
- * use one context share those tables: on one stream they are ordered; across
+ * and radii (the paper's batched grid over (Batch, h, w), Sec. 4.1 CUDA
+ * settings, extended to uneven jobs).  jobs is a HOST array of n entries
+ * (read before return); results are bit-identical to n separate me_estimate
+ * calls.  Jobs of equal shape (block, radius, frame size, pitches) share one
+ * launch of the full-search kernel over a (job, block row, block group) grid,
+ * with the launch shape me_estimate would use for that shape (autotuned ones
+ * included); the launches of all shapes, in order of first appearance, are
+ * captured once as one HIP graph and replayed while the job shapes repeat.
+ * Each workgroup reads its pair's pointers from a context-owned device table
+ * that each submission restages through pinned memory.  Submissions that use
+ * one context share that table: on one stream they are ordered; across
  * streams the caller must order them (or use one context per stream).
- * Returns ME_E_UNSUPPORTED for modes other than exhaustive step 1.
+ * Returns ME_E_UNSUPPORTED for jobs other than exhaustive step 1.
  */
 me_status me_batch_submit(me_ctx ctx, const me_job* jobs, int32_t n, void* stream);
 
@@ -484,6 +488,35 @@ me_status me_prnet_pw_backward(me_ctx ctx, const me_tensor* x, const me_tensor* 
  * dr (bfloat16, same shape) = dloss/dr; loss: device float. */
 me_status me_prnet_loss(me_ctx ctx, const float* r, const float* z_pred, const float* z_target, int32_t n, int32_t C,
                         int32_t Hf, int32_t Wf, float tau, uint16_t* dr, float* loss, void* stream);
+
+/*
+ * me_sync -- wait until the work enqueued on `stream` (NULL = the null
+ * stream) has finished.  Faults and launch failures of that asynchronous work
+ * surface here: ME_E_HIP with the runtime's message in me_last_error().
+ */
+me_status me_sync(void* stream);
+
+/*
+ * Training-set statistics of the learned-proposal mode, computed on the GPU
+ * from full-search SAD maps (device int32 [n][bh][bw] of n pairs of
+ * frame_h x frame_w Bayer samples with blocks of `block` packed pixels).
+ * The per-sample SAD of a block is q = sad / n_b in float32 (n_b = 4 h w, the
+ * block's sample count).
+ *
+ * me_sad_median: *median (device float) = the lower median of q over all
+ * n x bh x bw blocks (the element of rank floor((N-1)/2) in ascending order):
+ * the M of the SAD fallback test (me_refine).  Scratch in the context.
+ * me_fallback_weight: weight (device float32 [n][bh][bw]) = 1 where
+ * sad <= floor(sad_ratio * median_per_sample * n_b) (product in double, left
+ * to right: the SAD fallback threshold), else 0 -- blocks whose full-search
+ * match is worse than any accepted proposal could be, left out of the vector
+ * term of me_cnn_train_step.
+ * Both asynchronous on `stream`; ME_E_INVAL on bad sizes.
+ */
+me_status me_sad_median(me_ctx ctx, const int32_t* sad, int32_t n, int32_t block, int32_t frame_h, int32_t frame_w,
+                        float* median, void* stream);
+me_status me_fallback_weight(const int32_t* sad, int32_t n, int32_t block, int32_t frame_h, int32_t frame_w,
+                             float sad_ratio, float median_per_sample, float* weight, void* stream);
 
 /* Human-readable name of a status code (static string). */
 const char* me_status_string(me_status s);

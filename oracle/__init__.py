@@ -266,6 +266,24 @@ def block_samples(Hp, Wp, B):
     return 4 * hs[:, None].astype(np.int64) * ws[None, :]
 
 
+def median_per_sample(sad_maps, Hp, Wp, B):
+    """M of the SAD fallback test from full-search SAD maps ``[n, bh, bw]``:
+    the lower median (rank ``floor((N-1)/2)`` of the ascending values) of the
+    per-sample SAD ``sad / n_samples`` taken in float32."""
+    s = np.asarray(sad_maps).reshape(-1, *block_grid(Hp, Wp, B))
+    q = s.astype(np.float32) / block_samples(Hp, Wp, B).astype(np.float32)[None]
+    v = np.sort(q.ravel())
+    return np.float32(v[(v.size - 1) // 2])
+
+
+def fallback_weight(sad_maps, Hp, Wp, B, sad_ratio, median):
+    """1.0 where a block's full-search SAD is within the SAD fallback
+    threshold ``floor(ratio * M * n)``, else 0.0 (float32, shape of the maps)."""
+    s = np.asarray(sad_maps).reshape(-1, *block_grid(Hp, Wp, B))
+    thr = sad_threshold(sad_ratio, median, block_samples(Hp, Wp, B))
+    return (s.astype(np.int64) <= thr[None]).astype(np.float32)
+
+
 def decode_proposal(out_mv, R):
     """Proposal vector ``clamp(rint(8*o), -R, R)`` from the network's (mvx, mvy)
     output ``[2, bh, bw]`` (units of 8 packed pixels), rounding half to even."""

@@ -109,6 +109,7 @@ me_ctx_s::~me_ctx_s()
     (void)hipFree(tune_mv);
     (void)hipFree(tune_sad);
     (void)hipFree(prn_scratch);
+    (void)hipFree(stat);
 }
 
 namespace me {
@@ -145,17 +146,14 @@ TileCfg tiles_for(me_ctx ctx, int B, int R, int Hp, int Wp)
     return default_tiles(B, R);
 }
 
-me_status refine_impl(me_ctx ctx, const me_frame* ref, const me_frame* cur, const me_params& p, const float* net_out,
-                      int16_t* mv, int32_t* sad, uint8_t* fallback, hipStream_t st)
+me_status refine_run(const me_frame* ref, const me_frame* cur, const me_params& p, float m, const float* net_out,
+                     int16_t* mv, int32_t* sad, uint8_t* fallback, const RefineScratch& w, const TileCfg& full_tiles,
+                     hipStream_t st)
 {
-    const float m = p.sad_median_per_sample > 0.0f ? p.sad_median_per_sample : ctx->median_per_sample;
-    if (!(m > 0.0f)) return fail(ME_E_STATE, "refine: no SAD median (params or loaded weights)");
     const int Hp = cur->height / 2, Wp = cur->width / 2;
     const int bh = (Hp + p.block - 1) / p.block, bw = (Wp + p.block - 1) / p.block;
     const int nblk = bh * bw;
-    me_status s = ensure_scratch(ctx, (size_t)nblk);
-    if (s != ME_OK) return s;
-    uint8_t* fb = fallback ? fallback : ctx->fb;
+    uint8_t* fb = fallback ? fallback : w.fb;
 
     const double ratio_m = (double)p.sad_ratio * (double)m;
     hipError_t e;
@@ -166,24 +164,36 @@ me_status refine_impl(me_ctx ctx, const me_frame* ref, const me_frame* cur, cons
         e = launch_sad_search(a, default_tiles(p.block, p.refine_radius), nblk, st);
         if (e != hipSuccess) return hip_fail(e, "refine: refine search");
     } else {
-        e = launch_decode(net_out, nblk, p.radius, ctx->pred, st);
+        e = launch_decode(net_out, nblk, p.radius, w.pred, st);
         if (e != hipSuccess) return hip_fail(e, "refine: decode");
-        SearchArgs a = make_args(ref, cur, p.block, p.refine_radius, p.radius, ctx->pred, mv, sad);
+        SearchArgs a = make_args(ref, cur, p.block, p.refine_radius, p.radius, w.pred, mv, sad);
         e = launch_sad_search(a, default_tiles(p.block, p.refine_radius), nblk, st);
         if (e != hipSuccess) return hip_fail(e, "refine: refine search");
     }
-    e = launch_fallback(net_out, sad, bh, bw, Hp, Wp, p.block, p.conf_logit_thresh, ratio_m, fb, ctx->list,
-                        ctx->count, st);
+    e = launch_fallback(net_out, sad, bh, bw, Hp, Wp, p.block, p.conf_logit_thresh, ratio_m, fb, w.list, w.count, st);
     if (e != hipSuccess) return hip_fail(e, "refine: fallback");
     SearchArgs f = make_args(ref, cur, p.block, p.radius, p.radius, nullptr, mv, sad);
-    f.list = ctx->list;
-    f.list_n = ctx->count;
-    e = launch_sad_search(f, tiles_for(ctx, p.block, p.radius, Hp, Wp), nblk, st);
+    f.list = w.list;
+    f.list_n = w.count;
+    e = launch_sad_search(f, full_tiles, nblk, st);
     if (e != hipSuccess) return hip_fail(e, "refine: fallback search");
     return ME_OK;
 }
 
-static me_status check_refine_params(const me_params& p)
+me_status refine_impl(me_ctx ctx, const me_frame* ref, const me_frame* cur, const me_params& p, const float* net_out,
+                      int16_t* mv, int32_t* sad, uint8_t* fallback, hipStream_t st)
+{
+    const float m = p.sad_median_per_sample > 0.0f ? p.sad_median_per_sample : ctx->median_per_sample;
+    if (!(m > 0.0f)) return fail(ME_E_STATE, "refine: no SAD median (params or loaded weights)");
+    const int Hp = cur->height / 2, Wp = cur->width / 2;
+    const int bh = (Hp + p.block - 1) / p.block, bw = (Wp + p.block - 1) / p.block;
+    me_status s = ensure_scratch(ctx, (size_t)bh * bw);
+    if (s != ME_OK) return s;
+    const RefineScratch w{ctx->pred, ctx->fb, ctx->list, ctx->count};
+    return refine_run(ref, cur, p, m, net_out, mv, sad, fallback, w, tiles_for(ctx, p.block, p.radius, Hp, Wp), st);
+}
+
+me_status check_refine_params(const me_params& p)
 {
     if (!block_ok(p.block)) return fail(ME_E_UNSUPPORTED, "block %d not in {8,16,32,64}", p.block);
     if (p.radius < 0 || p.radius > 64) return fail(ME_E_INVAL, "radius %d not in [0,64]", p.radius);
@@ -648,6 +658,64 @@ me_status me_batch_submit(me_ctx ctx, const me_job* jobs, int32_t n, void* strea
         ctx->batch_slot.swap(slot);
     }
     if ((e = hipGraphLaunch(ctx->graph, st)) != hipSuccess) return hip_fail(e, "me_batch_submit: graph launch");
+    return ME_OK;
+}
+
+me_status me_sync(void* stream)
+{
+    hipError_t e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "me_sync: work on the stream failed");
+    return ME_OK;
+}
+
+namespace {
+
+me_status check_sad_maps(const char* who, const int32_t* sad, int32_t n, int32_t block, int32_t frame_h,
+                         int32_t frame_w, int* bh, int* bw)
+{
+    if (!sad) return fail(ME_E_INVAL, "%s: null sad", who);
+    if (n < 1) return fail(ME_E_INVAL, "%s: n = %d, need at least one map", who, n);
+    if (!block_ok(block)) return fail(ME_E_UNSUPPORTED, "%s: block %d not in {8,16,32,64}", who, block);
+    if (frame_h < 2 || frame_w < 2 || (frame_h & 1) || (frame_w & 1) || frame_h > 65536 || frame_w > 65536)
+        return fail(ME_E_INVAL, "%s: frame size must be even, 2..65536", who);
+    *bh = (frame_h / 2 + block - 1) / block;
+    *bw = (frame_w / 2 + block - 1) / block;
+    return ME_OK;
+}
+
+}  // namespace
+
+me_status me_sad_median(me_ctx ctx, const int32_t* sad, int32_t n, int32_t block, int32_t frame_h, int32_t frame_w,
+                        float* median, void* stream)
+{
+    if (!ctx || !median) return fail(ME_E_INVAL, "me_sad_median: null context or output");
+    int bh = 0, bw = 0;
+    me_status s = check_sad_maps("me_sad_median", sad, n, block, frame_h, frame_w, &bh, &bw);
+    if (s != ME_OK) return s;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if (!ctx->stat && hipMalloc(&ctx->stat, 260 * sizeof(uint32_t)) != hipSuccess)
+        return fail(ME_E_NOMEM, "me_sad_median: scratch allocation failed");
+    const int64_t N = (int64_t)n * bh * bw;
+    e = launch_sad_median(sad, N, bh * bw, bw, frame_h / 2, frame_w / 2, block, ctx->stat, ctx->stat + 256, median,
+                          reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "me_sad_median: launch");
+    return ME_OK;
+}
+
+me_status me_fallback_weight(const int32_t* sad, int32_t n, int32_t block, int32_t frame_h, int32_t frame_w,
+                             float sad_ratio, float median_per_sample, float* weight, void* stream)
+{
+    if (!weight) return fail(ME_E_INVAL, "me_fallback_weight: null weight");
+    int bh = 0, bw = 0;
+    me_status s = check_sad_maps("me_fallback_weight", sad, n, block, frame_h, frame_w, &bh, &bw);
+    if (s != ME_OK) return s;
+    if (!(sad_ratio >= 0.0f) || !(median_per_sample >= 0.0f))
+        return fail(ME_E_INVAL, "me_fallback_weight: ratio and median must be >= 0");
+    const double ratio_m = (double)sad_ratio * (double)median_per_sample;
+    hipError_t e = launch_fallback_weight(sad, (int64_t)n * bh * bw, bh * bw, bw, frame_h / 2, frame_w / 2, block,
+                                          ratio_m, weight, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "me_fallback_weight: launch");
     return ME_OK;
 }
 

@@ -86,6 +86,8 @@ struct me_ctx_s {
     // scratch of the single-layer network calls (packed weights, partials)
     void* prn_scratch = nullptr;
     size_t prn_scratch_cap = 0;
+    // median selection: 256 counters and the (prefix, rank) state
+    uint32_t* stat = nullptr;
     // autotune scratch outputs
     int16_t* tune_mv = nullptr;
     int32_t* tune_sad = nullptr;
@@ -97,6 +99,21 @@ struct me_ctx_s {
 namespace me {
 me_status ensure_scratch(me_ctx ctx, size_t nblk);
 TileCfg tiles_for(me_ctx ctx, int B, int R, int Hp, int Wp);
+// Device scratch of the refine + fallback step: decoded proposals (int16
+// [nblk][2], used for refine radii above 4), fallback flags (uint8 [nblk],
+// used when the caller passes none), the compacted fallback list (int32
+// [nblk]) and its count.
+struct RefineScratch {
+    int16_t* pred;
+    uint8_t* fb;
+    int32_t* list;
+    int32_t* count;
+};
+// Refine + fallback given the median m and the scratch; no allocation.
+me_status refine_run(const me_frame* ref, const me_frame* cur, const me_params& p, float m, const float* net_out,
+                     int16_t* mv, int32_t* sad, uint8_t* fallback, const RefineScratch& w, const TileCfg& full_tiles,
+                     hipStream_t st);
+me_status check_refine_params(const me_params& p);
 // Refine + fallback on a network output already in device memory.
 me_status refine_impl(me_ctx ctx, const me_frame* ref, const me_frame* cur, const me_params& p, const float* net_out,
                       int16_t* mv, int32_t* sad, uint8_t* fallback, hipStream_t st);

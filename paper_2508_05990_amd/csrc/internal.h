@@ -215,6 +215,14 @@ hipError_t launch_prloss(const float* r, const float* zp, const float* zt, int n
                          int32_t* nbad, uint32_t* maxbits, uint8_t* flags, uint16_t* dr, float* partial, float* loss,
                          hipStream_t st);
 
+// Training-set statistics (stats.hip): lower median of the per-sample SAD of
+// N = n * nblk blocks (hist: 256 counters, state: 2 words of scratch), and the
+// 0/1 weight sad <= floor(ratio_m * n_samples).
+hipError_t launch_sad_median(const int32_t* sad, int64_t N, int nblk, int bw, int Hp, int Wp, int B, uint32_t* hist,
+                             uint32_t* state, float* median, hipStream_t st);
+hipError_t launch_fallback_weight(const int32_t* sad, int64_t N, int nblk, int bw, int Hp, int Wp, int B,
+                                  double ratio_m, float* weight, hipStream_t st);
+
 hipError_t launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t stream);
 hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t stream);
 

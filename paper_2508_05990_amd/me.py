@@ -121,6 +121,9 @@ _me_prnet_pw_forward = _sig("me_prnet_pw_forward", [_P, _PT, _PT, _I32, _I32, _P
 _me_prnet_pw_backward = _sig("me_prnet_pw_backward", [_P, _PT, _PT, _PT, _I32, _I32, _P, _I32, _I32, _I32, _P, _P, _P,
                                                       _P, _P])
 _me_prnet_loss = _sig("me_prnet_loss", [_P, _P, _P, _P, _I32, _I32, _I32, _I32, _F, _P, _P, _P])
+_me_sync = _sig("me_sync", [_P])
+_me_sad_median = _sig("me_sad_median", [_P, _P, _I32, _I32, _I32, _I32, _P, _P])
+_me_fallback_weight = _sig("me_fallback_weight", [_P, _I32, _I32, _I32, _I32, _F, _F, _P, _P])
 _me_status_string = _sig("me_status_string", [_I32], ctypes.c_char_p)
 _me_last_error = _sig("me_last_error", [], ctypes.c_char_p)
 
@@ -133,7 +136,7 @@ EXPORTS = ["me_default_params", "me_ctx_create", "me_ctx_destroy", "me_estimate"
            "me_default_pyramid", "me_compose_vectors", "me_estimate_warp", "me_prnet_num_params", "me_prnet_create", "me_prnet_destroy",
            "me_prnet_set_params", "me_prnet_get_params", "me_prnet_forward", "me_prnet_train_step",
            "me_prnet_dw_forward", "me_prnet_dw_backward", "me_prnet_pw_forward", "me_prnet_pw_backward",
-           "me_prnet_loss"]
+           "me_prnet_loss", "me_sync", "me_sad_median", "me_fallback_weight"]
 ME_NHWC, ME_NCHW = 0, 1
 ME_CNN_NPARAMS = 21699
 
@@ -389,7 +392,41 @@ def batch_submit(ctx: Context, jobs, stream=None):
     _check(_me_batch_submit(ctx.handle, arr, len(arr), _stream_handle(stream)))
 
 
+def sync(stream=None):
+    """Wait for the stream's work; raises MeError (ME_E_HIP) if it failed."""
+    _check(_me_sync(_stream_handle(stream)))
+
+
 # --- proposal network ---------------------------------------------------------
+
+def _sad_maps(sad, block, frame_h, frame_w):
+    bh, bw = block_grid(frame_h, frame_w, block)
+    if sad.dtype != torch.int32 or not sad.is_contiguous() or sad.numel() % (bh * bw) or sad.numel() == 0:
+        raise ValueError("sad must be a contiguous int32 tensor of whole [%d, %d] maps" % (bh, bw))
+    return sad.numel() // (bh * bw)
+
+
+def sad_median(ctx: Context, sad, block, frame_h, frame_w, out=None, stream=None):
+    """Lower median of the per-sample full-search SAD over [n, bh, bw] maps
+    (device float32 scalar tensor, the M of the SAD fallback test)."""
+    n = _sad_maps(sad, block, frame_h, frame_w)
+    if out is None:
+        out = torch.empty((), dtype=torch.float32, device=sad.device)
+    _check(_me_sad_median(ctx.handle, sad.data_ptr(), n, block, frame_h, frame_w, out.data_ptr(),
+                          _stream_handle(stream)))
+    return out
+
+
+def fallback_weight(sad, block, frame_h, frame_w, sad_ratio, median_per_sample, out=None, stream=None):
+    """0/1 float32 weights [n, bh, bw]: 1 where the full-search SAD is within
+    the SAD fallback threshold floor(ratio * M * n_samples)."""
+    n = _sad_maps(sad, block, frame_h, frame_w)
+    if out is None:
+        out = torch.empty(sad.shape, dtype=torch.float32, device=sad.device)
+    _check(_me_fallback_weight(sad.data_ptr(), n, block, frame_h, frame_w, sad_ratio, median_per_sample,
+                               out.data_ptr(), _stream_handle(stream)))
+    return out
+
 
 def _p(t):
     return None if t is None else t.data_ptr()

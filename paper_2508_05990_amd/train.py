@@ -74,19 +74,22 @@ def _make_sequence(seed):
     return synth.hd_sequence(seed).frames
 
 
-def build_dataset(me, ctx, n_pairs, seed0, workers, log):
-    """Pooled inputs [n, 270, 480, 8] bf16 and full-search labels [n, 34, 60, 2] on the GPU."""
+def build_dataset(me, ctx, n_pairs, seed0, workers, log, H=1080, W=1920):
+    """Pooled inputs [n, H/4, W/4, 8] bf16 and full-search labels and SADs
+    [n, bh, bw] on the GPU, and the median per-sample SAD (library call)."""
     import torch
 
     n_seq = (n_pairs + 14) // 15
-    X = torch.empty((n_pairs, 270, 480, 8), dtype=torch.bfloat16, device="cuda")
-    Y = torch.empty((n_pairs, 34, 60, 2), dtype=torch.int16, device="cuda")
-    S = torch.empty((n_pairs, 34, 60), dtype=torch.int32, device="cuda")
+    bh, bw = me.block_grid(H, W, 16)
+    X = torch.empty((n_pairs, H // 4, W // 4, 8), dtype=torch.bfloat16, device="cuda")
+    Y = torch.empty((n_pairs, bh, bw, 2), dtype=torch.int16, device="cuda")
+    S = torch.empty((n_pairs, bh, bw), dtype=torch.int32, device="cuda")
     k = 0
     t0 = time.time()
     with ProcessPoolExecutor(max_workers=workers, mp_context=__import__("multiprocessing").get_context("spawn")) as ex:
         for si, frames in enumerate(ex.map(_make_sequence, [seed0 + s for s in range(n_seq)])):
             dev_frames = [torch.from_numpy(f).cuda() for f in frames]
+            assert dev_frames[0].shape == (H, W)
             for t in range(1, len(dev_frames)):
                 if k >= n_pairs:
                     break
@@ -96,11 +99,8 @@ def build_dataset(me, ctx, n_pairs, seed0, workers, log):
             torch.cuda.synchronize()
             if si % 20 == 0:
                 log({"event": "data", "sequences": si + 1, "pairs": k, "seconds": round(time.time() - t0, 1)})
-    # median over all blocks of the best SAD per sample (full blocks: 1024 samples; last row 768)
-    nsamp = torch.full((34, 60), 1024.0, device="cuda")
-    nsamp[-1] = 4.0 * 12 * 16
-    median = float(torch.median((S.float() / nsamp).flatten()).item())
-    return X, Y, S, nsamp, median
+    median = float(me.sad_median(ctx, S, 16, H, W).item())
+    return X, Y, S, median
 
 
 def evaluate(me, ctx, frames, use_net, median, R=32, rr=2, conf=0.0):
@@ -110,7 +110,7 @@ def evaluate(me, ctx, frames, use_net, median, R=32, rr=2, conf=0.0):
     import torch
 
     fb_sum = err_sum = n = 0
-    bh, bw = 34, 60
+    bh, bw = me.block_grid(frames[0].shape[0], frames[0].shape[1], 16)
     net_zero = torch.zeros((3, bh, bw), dtype=torch.float32, device="cuda")
     mv_e = torch.empty((bh, bw, 2), dtype=torch.int16, device="cuda")
     sad_e = torch.empty((bh, bw), dtype=torch.int32, device="cuda")
@@ -169,14 +169,13 @@ def main(argv=None):
 
     ctx = me.Context(0)
     t_all = time.time()
-    X, Y, S, nsamp, median = build_dataset(me, ctx, args.pairs, args.seed, args.workers, log)
+    X, Y, S, median = build_dataset(me, ctx, args.pairs, args.seed, args.workers, log)
     # vector-term weight: blocks whose full-search match is worse than the
     # fallback threshold always fall back, so their vectors (occlusions,
     # new content) are left out of the regression
     Wt = None
     if args.mask_ratio > 0:
-        thr = torch.floor(torch.tensor(args.mask_ratio, dtype=torch.float64) * median * nsamp.double())
-        Wt = (S.double() <= thr).float()
+        Wt = me.fallback_weight(S, 16, 1080, 1920, args.mask_ratio, median)
     log({"event": "dataset", "pairs": args.pairs, "median_sad_per_sample": median,
          "vector_weight_mean": None if Wt is None else float(Wt.mean().item())})
     me.cnn_set_params(ctx, init_params(args.init_seed), median)

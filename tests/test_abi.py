@@ -267,3 +267,15 @@ def test_tuned_shape_validation(me):
     assert put((ctypes.c_int32 * 4)(4, 4, 1, 0)) == 2                     # no LDS budget
     assert put((ctypes.c_int32 * 4)(4, 4, 1, 159)) == 2                   # beyond the LDS of a workgroup
     assert put((ctypes.c_int32 * 4)(4, 4, 1, 1)) == 2                     # no band fits 1 KB
+
+
+def test_stats_validation(me):
+    fake_ctx = ctypes.c_void_p(FAKE)
+    assert me._me_sad_median(None, FAKE, 1, 16, 1080, 1920, FAKE, None) == 1      # needs a context
+    assert me._me_sad_median(fake_ctx, 0, 1, 16, 1080, 1920, FAKE, None) == 1     # null sad
+    assert me._me_sad_median(fake_ctx, FAKE, 0, 16, 1080, 1920, FAKE, None) == 1  # no maps
+    assert me._me_sad_median(fake_ctx, FAKE, 1, 12, 1080, 1920, FAKE, None) == 2  # block size
+    assert me._me_sad_median(fake_ctx, FAKE, 1, 16, 1079, 1920, FAKE, None) == 1  # odd frame
+    assert me._me_fallback_weight(FAKE, 1, 16, 1080, 1920, 1.5, 1.0, 0, None) == 1
+    assert me._me_fallback_weight(FAKE, 1, 16, 1080, 1920, -1.0, 1.0, FAKE, None) == 1
+    assert me._me_fallback_weight(FAKE, 1, 16, 1080, 1920, 1.5, float("nan"), FAKE, None) == 1

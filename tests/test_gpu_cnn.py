@@ -294,3 +294,89 @@ def test_training_is_deterministic_and_resumable(dev, ctx):
     finally:
         c2.close()
     assert np.array_equal(r, a)
+
+
+# Grids the batch-16 1080p training step runs: at 1024 or more 64-pixel tiles
+# the forward takes the unsplit kernel (one wave per 16 output pixels), and
+# beyond 256 chunks of 64 output pixels each weight-gradient workgroup walks
+# several chunks before its partial is reduced.  (layer, n, H, W) below give
+# 1519, 1148, 1148 and 1052 forward tiles, and 1013, 383, 287 and 287 chunks.
+FULL_FWD = [(0, 3, 270, 480), (1, 9, 135, 240), (2, 36, 68, 120), (3, 33, 34, 60)]
+FULL_BWD = [(0, 2, 270, 480), (1, 3, 135, 240), (2, 9, 68, 120), (3, 9, 34, 60)]
+
+
+@pytest.mark.parametrize("layer,n,H,W", FULL_FWD)
+def test_layer_forward_full_grid(dev, ctx, layer, n, H, W):
+    """Each layer's forward element by element on a grid large enough for the
+    unsplit forward kernel, inputs of the 1080p network's shapes."""
+    import torch
+
+    params = _params(11)
+    dev.cnn_set_params(ctx, params, 1.0)
+    ci, co, s = cnn.LAYERS[layer]
+    Ho, Wo = cnn.out_size(H, s), cnn.out_size(W, s)
+    assert (n * Ho * Wo + 63) // 64 >= 1024
+    rng = np.random.default_rng(100 + layer)
+    x = cnn.bf16_round(rng.normal(0, 1, (n, ci, H, W)))
+    if layer > 0:
+        x = np.maximum(x, 0)
+    if layer < 3:
+        out = torch.empty((n, Ho, Wo, co), dtype=torch.bfloat16, device="cuda")
+    else:
+        out = torch.empty((n, co, Ho, Wo), dtype=torch.float32, device="cuda")
+    print("forward layer %d on %d x %dx%d" % (layer, n, H, W), flush=True)
+    dev.cnn_layer_forward(ctx, layer, _bf(_nhwc(x)), out)
+    torch.cuda.synchronize()
+    got = _nchw(_np(out)) if layer < 3 else _np(out)
+    Wl, bl = cnn.unpack(params)[layer]
+    Wr = cnn.bf16_round(Wl)
+    for i in range(n):
+        z = cnn.conv3x3(x[i], Wr, bl, s)
+        ab = cnn.conv3x3_abs(x[i], Wr, bl, s)
+        ref = np.maximum(z, 0) if layer < 3 else z
+        bound = (U * np.abs(ref) if layer < 3 else 0) + 2e-5 * ab + 1e-30
+        assert (np.abs(got[i] - ref) <= bound).all(), (i, np.abs(got[i] - ref).max())
+
+
+@pytest.mark.parametrize("layer,n,H,W", FULL_BWD)
+def test_layer_backward_many_chunks(dev, ctx, layer, n, H, W):
+    """Weight, bias and input gradients element by element with more than 256
+    chunks of output pixels (several per weight-gradient workgroup).  A float32
+    sum of the per-chunk products over c chunks per workgroup, then over 256
+    workgroups, has at most ~4c + 272 rounding steps: within 1e-4 sum|terms|
+    for c up to 5."""
+    import torch
+
+    params = _params(12)
+    dev.cnn_set_params(ctx, params, 1.0)
+    ci, co, s = cnn.LAYERS[layer]
+    coutp = 4 if layer == 3 else co
+    Ho, Wo = cnn.out_size(H, s), cnn.out_size(W, s)
+    assert (n * Ho * Wo + 63) // 64 > 256
+    rng = np.random.default_rng(200 + layer)
+    x = cnn.bf16_round(np.maximum(rng.normal(0, 1, (n, ci, H, W)), 0) if layer > 0 else rng.normal(0, 1, (n, ci, H, W)))
+    dz = cnn.bf16_round(rng.normal(0, 1e-3, (n, coutp, Ho, Wo)))
+    if layer == 3:
+        dz[:, 3] = 0.0
+    grads = torch.zeros(cnn.NPARAMS, dtype=torch.float32, device="cuda")
+    dx = torch.empty((n, H, W, ci), dtype=torch.bfloat16, device="cuda") if layer > 0 else None
+    print("backward layer %d on %d x %dx%d" % (layer, n, H, W), flush=True)
+    dev.cnn_layer_backward(ctx, layer, _bf(_nhwc(x)), _bf(_nhwc(dz)), dx, grads)
+    torch.cuda.synchronize()
+    g = grads.cpu().numpy().astype(np.float64)
+    Wl, _ = cnn.unpack(params)[layer]
+    d = dz[:, :co]
+    dW = sum(cnn.conv_wgrad(x[i], d[i], s) for i in range(n))
+    dWa = sum(cnn.conv_wgrad(np.abs(x[i]), np.abs(d[i]), s) for i in range(n))
+    db = d.sum(axis=(0, 2, 3))
+    dba = np.abs(d).sum(axis=(0, 2, 3))
+    gl = cnn.unpack(g)[layer]
+    assert (np.abs(gl[0] - dW) <= 1e-4 * dWa + 1e-30).all(), np.abs(gl[0] - dW).max()
+    assert (np.abs(gl[1] - db) <= 1e-4 * dba + 1e-30).all()
+    if layer > 0:
+        got = _nchw(_np(dx))
+        Wr = cnn.bf16_round(Wl)
+        for i in range(n):
+            ref = cnn.conv_dgrad(d[i], Wr, s, x[i].shape) * (x[i] > 0)
+            ab = cnn.conv_dgrad(np.abs(d[i]), np.abs(Wr), s, x[i].shape)
+            assert (np.abs(got[i] - ref) <= U * np.abs(ref) + 2e-5 * ab + 1e-30).all(), i

@@ -156,21 +156,22 @@ def test_hd_sequence_pairs_bit_exact(dev, oracle_mod, hd_seq):
         _assert_same(mv_g, sad_g, mv_o, sad_o)
 
 
-def test_uhd_sampled_blocks_bit_exact(dev, oracle_mod):
-    """4K, B=16, R=64 (the LDS window is processed in dy bands): three pairs,
-    all border blocks plus a seeded sample of interior blocks."""
+@pytest.fixture(scope="module")
+def uhd_seq():
     from paper_2508_05990_amd import synth
 
-    seq = synth.uhd_sequence(4, n_frames=4)
-    bh, bw = 68, 120
-    rng = np.random.default_rng(0)
-    border = [i * bw + j for i in range(bh) for j in range(bw) if i in (0, 1, bh - 2, bh - 1) or j in (0, 1, bw - 2, bw - 1)]
-    idx = np.unique(np.concatenate([border, rng.choice(bh * bw, 150, replace=False)])).astype(np.int32)
-    for t in (1, 2, 3):
-        print("4K pair", t, flush=True)
-        mv_g, sad_g = _gpu_full(dev, seq.frames[t - 1], seq.frames[t], 16, 64)
-        mv_o, sad_o, _ = oracle_mod.full_search(seq.frames[t - 1], seq.frames[t], 16, 64, blocks=idx)
-        _assert_same(mv_g, sad_g, mv_o, sad_o, blocks=idx)
+    return synth.uhd_sequence(4, n_frames=4)
+
+
+@pytest.mark.parametrize("t", [1, 2, 3])
+def test_uhd_pairs_bit_exact(dev, oracle_mod, uhd_seq, t):
+    """4K, B=16, R=64 (the LDS window is processed in dy bands): three pairs
+    of the panning 4K sequence, every block of the frame."""
+    print("4K pair", t, flush=True)
+    mv_g, sad_g = _gpu_full(dev, uhd_seq.frames[t - 1], uhd_seq.frames[t], 16, 64)
+    mv_o, sad_o, ops = oracle_mod.full_search(uhd_seq.frames[t - 1], uhd_seq.frames[t], 16, 64)
+    assert ops == 130_206_208_000
+    _assert_same(mv_g, sad_g, mv_o, sad_o)
 
 
 @pytest.mark.parametrize("B", [8, 32, 64])

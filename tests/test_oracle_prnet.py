@@ -203,3 +203,117 @@ def test_relu6_derivative_convention_and_planes():
     assert pl[0, 1, 2, 0] == (int(m[2, 4]) - 2048) / 1024 and pl[0, 1, 2, 3] == (int(m[3, 5]) - 2048) / 1024
     assert P.feature_grid(540, 960) == (135, 240)
     assert P.feature_grid(11, 5) == (3, 2)
+
+
+# ---- rounded backward: float64 autograd with bfloat16 store points ---------
+#
+# The kernels store activations and the gradients that reach them in
+# bfloat16.  This pin rebuilds the network in torch (float64, CPU) from the
+# library convolutions and lets autograd derive the whole backward pass; the
+# only hand-placed parts are the store points themselves, each a torch
+# function whose forward rounds the value (torch's bfloat16 cast) and whose
+# backward rounds the gradient that reaches the stored tensor:
+#   ReLU6 layers: the gradient at the pre-activation, after the ReLU6 mask
+#   read from the stored output; linear block outputs: the total gradient;
+#   1x1 weights: rounded in the forward, gradient passed straight through.
+
+
+def _rb(t):
+    return t.to(torch.bfloat16).to(torch.float64)
+
+
+class _StoreRelu6(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x):
+        y = _rb(x.clamp(0.0, 6.0))
+        ctx.save_for_backward(y)
+        return y
+
+    @staticmethod
+    def backward(ctx, g):
+        (y,) = ctx.saved_tensors
+        return _rb(g * ((y > 0) & (y < 6)).to(g.dtype))
+
+
+class _StoreLinear(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x):
+        return _rb(x)
+
+    @staticmethod
+    def backward(ctx, g):
+        return _rb(g)
+
+
+class _WeightRound(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, w):
+        return _rb(w)
+
+    @staticmethod
+    def backward(ctx, g):
+        return g
+
+
+def _torch_rounded_grad(p, cfg, m, z, dr, store=True):
+    """Flat parameter gradient of <dr, r> through the network built in torch;
+    store=False leaves out every rounding (for the sensitivity check)."""
+    F = torch.nn.functional
+    sr = _StoreRelu6.apply if store else (lambda x: x.clamp(0.0, 6.0))
+    sl = _StoreLinear.apply if store else (lambda x: x)
+    wr = _WeightRound.apply if store else (lambda w: w)
+    fr = _rb if store else (lambda x: x)
+    specs = P.layer_specs(cfg)
+    leaves, k = [], 0
+    flat = torch.from_numpy(np.asarray(p, dtype=np.float64))
+    for kind, ci, co, _, _ in specs:
+        nw = co * 9 if kind == "dw" else co * ci
+        W = flat[k:k + nw].clone().reshape((co, 1, 3, 3) if kind == "dw" else (co, ci)).requires_grad_(True)
+        b = flat[k + nw:k + nw + co].clone().requires_grad_(True)
+        leaves.append((W, b))
+        k += nw + co
+
+    def dw(x, i, s):                                    # NCHW depthwise, zero padding 1
+        W, b = leaves[i]
+        return F.conv2d(x, W, b, stride=s, padding=1, groups=x.shape[1])
+
+    def pw(x, i):                                       # NCHW 1x1 on rounded weights
+        W, b = leaves[i]
+        return torch.einsum("oc,nchw->nohw", wr(W), x) + b[None, :, None, None]
+
+    mt = torch.from_numpy(np.asarray(m, dtype=np.float64))
+    planes = torch.stack([mt[:, 0::2, 0::2], mt[:, 0::2, 1::2], mt[:, 1::2, 0::2], mt[:, 1::2, 1::2]], dim=1)
+    a0 = fr((planes - 2048.0) / 1024.0)
+    e1 = sr(dw(a0, 0, 2))
+    e2 = sr(pw(e1, 1))
+    e3 = sr(dw(e2, 2, 2))
+    e4 = sr(pw(e3, 3))
+    xc = torch.cat([fr(torch.from_numpy(np.asarray(z, dtype=np.float64))), e4], dim=1)
+    h = sr(pw(xc, 4))
+    for blk in range(cfg.n_blocks):
+        i = 5 + 3 * blk
+        u = sr(pw(h, i))
+        v = sr(dw(u, i + 1, 1))
+        h = sl(pw(v, i + 2) + h)
+    r = pw(h, len(specs) - 1)
+    r.backward(fr(torch.from_numpy(np.asarray(dr, dtype=np.float64))))
+    parts = []
+    for W, b in leaves:
+        parts += [W.grad.reshape(-1).numpy(), b.grad.numpy()]
+    return np.concatenate(parts)
+
+
+@pytest.mark.parametrize("seed,tau", [(3, -1.0), (4, 0.1)])
+def test_rounded_backward_matches_autograd_with_store_points(seed, tau):
+    m, z, zt = _inputs(seed, n=2, H=28, W=44)
+    p = P.init_params(CFG, seed).astype(np.float64)
+    A, r, _ = P.forward(p, CFG, m, z)                   # bfloat16 store points (the default)
+    _, dr, _ = P.loss_and_grad(r, z, zt, tau)
+    g = P.backward(p, CFG, A, dr)
+    ref = _torch_rounded_grad(p, CFG, m, z, dr)
+    scale = np.abs(ref).max()
+    np.testing.assert_allclose(g, ref, rtol=1e-9, atol=1e-12 * scale)
+    # the pin can tell: without the store points the gradient moves by far more
+    # than the tolerance (a misplaced rounding would show)
+    plain = _torch_rounded_grad(p, CFG, m, z, dr, store=False)
+    assert np.abs(plain - ref).max() > 1e-4 * scale

@@ -81,3 +81,33 @@ def test_sad_threshold(oracle_mod):
     t = oracle_mod.sad_threshold(1.5, 2.0, n)
     assert t[0, 0] == 3072 and t[-1, 0] == 2304
     assert oracle_mod.sad_threshold(1.5, 1.1, 1000) == 1650
+
+
+def test_median_per_sample_is_the_lower_median(oracle_mod):
+    """Hand-computed cases: odd and even counts, partial blocks (fewer
+    samples), and a brute-force rank count on random maps."""
+    # 2 x 2 blocks of 16 on a 24 x 24 packed frame: samples 1024, 512 / 512, 256
+    n = np.array([[1024, 512], [512, 256]])
+    sad = (np.array([[3, 1], [4, 2]]) * n)[None]          # per sample 3, 1, 4, 2
+    assert oracle_mod.median_per_sample(sad, 24, 24, 16) == np.float32(2.0)     # lower of 2, 3
+    sad3 = np.concatenate([sad, (np.array([[5, 5], [5, 5]]) * n)[None]])
+    assert oracle_mod.median_per_sample(sad3, 24, 24, 16) == np.float32(4.0)    # 1,2,3,4,5,5,5,5: rank 3
+    rng = np.random.default_rng(0)
+    maps = rng.integers(0, 400000, size=(5, 4, 6)).astype(np.int32)
+    m = oracle_mod.median_per_sample(maps, 60, 90, 16)
+    q = [np.float32(maps[k, i, j]) / np.float32(4 * min(16, 60 - 16 * i) * min(16, 90 - 16 * j))
+         for k in range(5) for i in range(4) for j in range(6)]
+    below = sum(v < m for v in q)
+    at_or_below = sum(v <= m for v in q)
+    assert below <= (len(q) - 1) // 2 < at_or_below
+    assert m in q
+
+
+def test_fallback_weight_threshold(oracle_mod):
+    n = np.array([[1024, 512], [512, 256]])
+    M = np.float32(1.7)
+    thr = np.floor(1.5 * 1.7 * n.astype(np.float64))
+    sad = np.stack([thr, thr + 1]).astype(np.int32)
+    w = oracle_mod.fallback_weight(sad, 24, 24, 16, 1.5, M)
+    assert w.dtype == np.float32 and w.shape == (2, 2, 2)
+    assert (w[0] == 1).all() and (w[1] == 0).all()
