@@ -32,6 +32,11 @@ SAD_TRAFFIC = {"source_sha256_16": "29c5caaddb65448c", "bytes": 7947.54 * 1024 *
 SAD_SOURCE = os.path.join(ROOT, "paper_2508_05990_amd", "csrc", "sad_search.hip")
 
 
+def progress(msg):
+    """One line per finished leg on stderr (the JSON result line stays alone on stdout)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
 def sad_traffic():
     import hashlib
 
@@ -785,28 +790,26 @@ def main():
                                     / (wall / (npairs * args.steps)), 4),
     }
     args.hd_mvs = mvs
-    if not args.no_bf16_step:
-        res["bf16_warp_step"] = bf16_step_leg(me, ctx, frames, mvs, sads, B, R, H, W, args)
-    if not args.no_warp_hbm:
-        res["warp_hbm"] = warp_hbm_leg(me, ctx, args)
-    if not args.no_fused:
-        res["fused_search_warp"] = fused_leg(me, ctx, frames, z, mvs, sads, outs, B, R, H, W, args)
-    if not args.no_proposal:
-        res["proposal"] = proposal_leg(me, ctx, frames, mvs, z, outs, B, R, H, W, args)
-    if not args.no_pyramid:
-        res["pyramid"] = pyramid_leg(me, ctx, frames, mvs, z, outs, B, R, H, W, args)
-    if not args.no_gop:
-        res["gop_propagation"] = gop_leg(me, ctx, frames, B, R, args)
-    if not args.no_prnet:
-        res["prnet"] = prnet_leg(me, ctx, frames, z, mvs, B, H, W, args)
-    if not args.no_paper_shapes:
-        res["paper_shapes"] = paper_shapes_leg(me, ctx, args)
-    if not args.no_batched:
-        res["batched_streams"] = batched_leg(me, ctx, args)
-    if args.uhd_frames > 1:
-        res["uhd"] = uhd_leg(me, ctx, args)
-    if args.cpu_seconds > 0:
-        res["cpu_baseline"] = cpu_baseline(seq.frames, feats, B, R, args.cpu_seconds)
+    progress("headline: %.1f frames/s, search %.4f ms per pair" % (res["value"], me_avg))
+    legs = [
+        ("bf16_warp_step", not args.no_bf16_step, lambda: bf16_step_leg(me, ctx, frames, mvs, sads, B, R, H, W, args)),
+        ("warp_hbm", not args.no_warp_hbm, lambda: warp_hbm_leg(me, ctx, args)),
+        ("fused_search_warp", not args.no_fused,
+         lambda: fused_leg(me, ctx, frames, z, mvs, sads, outs, B, R, H, W, args)),
+        ("proposal", not args.no_proposal, lambda: proposal_leg(me, ctx, frames, mvs, z, outs, B, R, H, W, args)),
+        ("pyramid", not args.no_pyramid, lambda: pyramid_leg(me, ctx, frames, mvs, z, outs, B, R, H, W, args)),
+        ("gop_propagation", not args.no_gop, lambda: gop_leg(me, ctx, frames, B, R, args)),
+        ("prnet", not args.no_prnet, lambda: prnet_leg(me, ctx, frames, z, mvs, B, H, W, args)),
+        ("paper_shapes", not args.no_paper_shapes, lambda: paper_shapes_leg(me, ctx, args)),
+        ("batched_streams", not args.no_batched, lambda: batched_leg(me, ctx, args)),
+        ("uhd", args.uhd_frames > 1, lambda: uhd_leg(me, ctx, args)),
+        ("cpu_baseline", args.cpu_seconds > 0, lambda: cpu_baseline(seq.frames, feats, B, R, args.cpu_seconds)),
+    ]
+    for name, on, run in legs:
+        if on:
+            t_leg = time.perf_counter()
+            res[name] = run()
+            progress("%s done in %.1f s" % (name, time.perf_counter() - t_leg))
     ctx.close()
     print(json.dumps(res), flush=True)
 

@@ -68,13 +68,24 @@ def cosine_lr(step, total, lr0, lr_min):
     return lr_min + 0.5 * (lr0 - lr_min) * (1.0 + math.cos(math.pi * t))
 
 
-def _make_sequence(seed):
+def _make_sequence(spec):
+    """Frames of one training sequence: the 1080p generator (8 rectangles,
+    |v| <= 24), with a seeded background pan of up to pan_max packed pixels
+    per component per frame when pan_max > 0."""
     from paper_2508_05990_amd import synth
 
-    return synth.hd_sequence(seed).frames
+    seed, pan_max = spec
+    return synth.sequence(seed, 1080, 1920, 16, 8, (48, 192), 24, 2.0, pan_max=pan_max).frames
 
 
-def build_dataset(me, ctx, n_pairs, seed0, workers, log, H=1080, W=1920):
+def sequence_specs(n_seq, seed0, pan_max, pan_every):
+    """(seed, pan_max) per training sequence: every pan_every-th sequence pans
+    (pan_every = 0: none does)."""
+    return [(seed0 + s, pan_max if pan_max > 0 and pan_every > 0 and s % pan_every == 0 else 0)
+            for s in range(n_seq)]
+
+
+def build_dataset(me, ctx, n_pairs, seed0, workers, log, H=1080, W=1920, pan_max=0, pan_every=0):
     """Pooled inputs [n, H/4, W/4, 8] bf16 and full-search labels and SADs
     [n, bh, bw] on the GPU, and the median per-sample SAD (library call)."""
     import torch
@@ -87,7 +98,7 @@ def build_dataset(me, ctx, n_pairs, seed0, workers, log, H=1080, W=1920):
     k = 0
     t0 = time.time()
     with ProcessPoolExecutor(max_workers=workers, mp_context=__import__("multiprocessing").get_context("spawn")) as ex:
-        for si, frames in enumerate(ex.map(_make_sequence, [seed0 + s for s in range(n_seq)])):
+        for si, frames in enumerate(ex.map(_make_sequence, sequence_specs(n_seq, seed0, pan_max, pan_every))):
             dev_frames = [torch.from_numpy(f).cuda() for f in frames]
             assert dev_frames[0].shape == (H, W)
             for t in range(1, len(dev_frames)):
@@ -135,6 +146,65 @@ def evaluate(me, ctx, frames, use_net, median, R=32, rr=2, conf=0.0):
     return {"fallback_rate": fb_sum / n, "mv_err_rate": err_sum / n, "ms_per_pair": float(np.median(times))}
 
 
+def fit(me, ctx, X, Y, Wt, median, epochs, batch, lr0, lr_min, seed, init_seed, refine_radius, log):
+    """AdamW with a cosine learning rate over `epochs` passes of shuffled
+    batches (the library's training step); returns the float32 parameters."""
+    import torch
+
+    me.cnn_set_params(ctx, init_params(init_seed), median)
+    n = X.shape[0]
+    steps_per_epoch = n // batch
+    total = steps_per_epoch * epochs
+    rng = np.random.default_rng(seed)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    xb = torch.empty((batch,) + tuple(X.shape[1:]), dtype=X.dtype, device="cuda")
+    yb = torch.empty((batch,) + tuple(Y.shape[1:]), dtype=Y.dtype, device="cuda")
+    wb = None if Wt is None else torch.empty((batch,) + tuple(Wt.shape[1:]), dtype=Wt.dtype, device="cuda")
+    step = 0
+    lr = lr0
+    t0 = time.time()
+    for ep in range(epochs):
+        order = torch.from_numpy(rng.permutation(n)).cuda()
+        for s in range(steps_per_epoch):
+            idx = order[s * batch:(s + 1) * batch]
+            torch.index_select(X, 0, idx, out=xb)
+            torch.index_select(Y, 0, idx, out=yb)
+            if wb is not None:
+                torch.index_select(Wt, 0, idx, out=wb)
+            lr = cosine_lr(step, total, lr0, lr_min)
+            me.cnn_train_step(ctx, xb, yb, radius=32, refine_radius=refine_radius, lr=lr, update=True,
+                              loss=loss if s == steps_per_epoch - 1 else None, weight=wb)
+            step += 1
+        if ep % max(1, epochs // 20) == 0 or ep == epochs - 1:
+            log({"event": "epoch", "epoch": ep, "step": step, "lr": lr, "loss": float(loss.item()),
+                 "seconds": round(time.time() - t0, 1)})
+    torch.cuda.synchronize()
+    params, _ = me.cnn_get_params(ctx)
+    return params, total, time.time() - t0
+
+
+def evaluate_all(me, ctx, median, rr, eval_seed, uhd_frames, log):
+    """Held-out 1080p sequence (R=32) and, if uhd_frames > 1, the first frames
+    of the 4K sequence with a background pan (R=64): the trained network with
+    both fallbacks, with the SAD fallback only, and zero proposals."""
+    import torch
+
+    from paper_2508_05990_amd import synth
+
+    out = {}
+    cases = [("hd", synth.hd_sequence(eval_seed), 32)]
+    if uhd_frames > 1:
+        cases.append(("uhd", synth.uhd_sequence(4, n_frames=uhd_frames), 64))
+    for name, seq, R in cases:
+        frames = [torch.from_numpy(f).cuda() for f in seq.frames]
+        out[name] = {"trained": evaluate(me, ctx, frames, True, median, R=R, rr=rr),
+                     "trained_sad_fallback_only": evaluate(me, ctx, frames, True, median, R=R, rr=rr, conf=-1e30),
+                     "zero_predictor": evaluate(me, ctx, frames, False, median, R=R, rr=rr)}
+        log({"event": "eval", "sequence": name, **out[name]})
+        del frames
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--pairs", type=int, default=2000)
@@ -145,7 +215,11 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=1000, help="first sequence seed of the training set")
     ap.add_argument("--init-seed", type=int, default=0)
     ap.add_argument("--eval-seed", type=int, default=1, help="held-out 1080p sequence")
+    ap.add_argument("--eval-uhd-frames", type=int, default=0, help="also evaluate on this many 4K frames (0 = no)")
     ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--pan-max", type=int, default=0,
+                    help="background pan of up to this many packed pixels per frame in some training sequences")
+    ap.add_argument("--pan-every", type=int, default=2, help="every n-th training sequence pans (with --pan-max)")
     ap.add_argument("--refine-radius", type=int, default=2, help="refine window of the confidence labels")
     ap.add_argument("--mask-ratio", type=float, default=1.5,
                     help="drop the vector term of blocks whose full-search SAD per sample exceeds this multiple "
@@ -163,64 +237,31 @@ def main(argv=None):
             logf.write(line + "\n")
             logf.flush()
 
-    import torch
-
-    from paper_2508_05990_amd import me, synth
+    from paper_2508_05990_amd import me
 
     ctx = me.Context(0)
     t_all = time.time()
-    X, Y, S, median = build_dataset(me, ctx, args.pairs, args.seed, args.workers, log)
+    X, Y, S, median = build_dataset(me, ctx, args.pairs, args.seed, args.workers, log, pan_max=args.pan_max,
+                                    pan_every=args.pan_every)
     # vector-term weight: blocks whose full-search match is worse than the
     # fallback threshold always fall back, so their vectors (occlusions,
     # new content) are left out of the regression
     Wt = None
     if args.mask_ratio > 0:
         Wt = me.fallback_weight(S, 16, 1080, 1920, args.mask_ratio, median)
-    log({"event": "dataset", "pairs": args.pairs, "median_sad_per_sample": median,
+    log({"event": "dataset", "pairs": args.pairs, "median_sad_per_sample": median, "pan_max": args.pan_max,
+         "pan_every": args.pan_every,
          "vector_weight_mean": None if Wt is None else float(Wt.mean().item())})
-    me.cnn_set_params(ctx, init_params(args.init_seed), median)
-
-    steps_per_epoch = args.pairs // args.batch
-    total = steps_per_epoch * args.epochs
-    rng = np.random.default_rng(args.seed)
-    loss = torch.empty(1, dtype=torch.float32, device="cuda")
-    xb = torch.empty((args.batch,) + tuple(X.shape[1:]), dtype=X.dtype, device="cuda")
-    yb = torch.empty((args.batch,) + tuple(Y.shape[1:]), dtype=Y.dtype, device="cuda")
-    wb = None if Wt is None else torch.empty((args.batch,) + tuple(Wt.shape[1:]), dtype=Wt.dtype, device="cuda")
-    step = 0
-    t0 = time.time()
-    for ep in range(args.epochs):
-        order = torch.from_numpy(rng.permutation(args.pairs)).cuda()
-        for s in range(steps_per_epoch):
-            idx = order[s * args.batch:(s + 1) * args.batch]
-            torch.index_select(X, 0, idx, out=xb)
-            torch.index_select(Y, 0, idx, out=yb)
-            if wb is not None:
-                torch.index_select(Wt, 0, idx, out=wb)
-            lr = cosine_lr(step, total, args.lr, args.lr_min)
-            me.cnn_train_step(ctx, xb, yb, radius=32, refine_radius=args.refine_radius, lr=lr, update=True,
-                              loss=loss if s == steps_per_epoch - 1 else None, weight=wb)
-            step += 1
-        if ep % 5 == 0 or ep == args.epochs - 1:
-            log({"event": "epoch", "epoch": ep, "step": step, "lr": lr, "loss": float(loss.item()),
-                 "seconds": round(time.time() - t0, 1)})
-    torch.cuda.synchronize()
-    train_s = time.time() - t0
-    params, med = me.cnn_get_params(ctx)
+    params, total, train_s = fit(me, ctx, X, Y, Wt, median, args.epochs, args.batch, args.lr, args.lr_min, args.seed,
+                                 args.init_seed, args.refine_radius, log)
+    del X
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
-    save_weights(args.out, params, med)
-
-    seq = synth.hd_sequence(args.eval_seed)
-    frames = [torch.from_numpy(f).cuda() for f in seq.frames]
-    rr = args.refine_radius
-    trained = evaluate(me, ctx, frames, True, med, rr=rr)
-    zero = evaluate(me, ctx, frames, False, med, rr=rr)
-    trained_sad_only = evaluate(me, ctx, frames, True, med, rr=rr, conf=-1e30)
+    save_weights(args.out, params, median)
+    res = evaluate_all(me, ctx, median, args.refine_radius, args.eval_seed, args.eval_uhd_frames, log)
     log({"event": "done", "train_seconds": round(train_s, 1), "total_seconds": round(time.time() - t_all, 1),
-         "steps": total, "weights": args.out, "refine_radius": rr, "heldout_trained": trained,
-         "heldout_zero_predictor": zero, "heldout_trained_sad_fallback_only": trained_sad_only})
+         "steps": total, "weights": args.out, "refine_radius": args.refine_radius, "heldout": res})
     ctx.close()
-    return trained, zero
+    return res
 
 
 if __name__ == "__main__":
