@@ -234,6 +234,29 @@ me_status me_refine(me_ctx ctx, const me_frame* ref, const me_frame* cur, const 
                     const float* net_out, int16_t* mv, int32_t* sad, uint8_t* fallback, void* stream);
 
 /*
+ * me_refine_noalloc -- me_refine for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, steps, kernels and results (bit for bit)
+ * as me_refine, but the step's scratch (decoded proposals, fallback flags,
+ * the fallback list and its count) lives in a fixed device array of the
+ * library, 9 * ME_NOALLOC_MAX_BLOCKS + 256 bytes (576 KiB) on each device the
+ * library runs on, held until the process ends, instead of context buffers
+ * grown with hipMalloc.  The call allocates nothing, host or device.
+ *   - ME_E_INVAL if the frame has more than ME_NOALLOC_MAX_BLOCKS blocks
+ *     (checked before the context), and for the arguments me_refine rejects.
+ *   - The array's address is resolved by me_ctx_create for the context's
+ *     device; kernels run on `stream`, which must belong to that device.
+ *   - Every call on one device shares that device's array and leaves the last
+ *     call's contents in it (each call rewrites the count and the list it
+ *     reads): calls that overlap on one device -- different streams, host
+ *     threads or contexts without ordering between them -- race.  Order them
+ *     on one stream.
+ */
+#define ME_NOALLOC_MAX_BLOCKS 65536
+me_status me_refine_noalloc(me_ctx ctx, const me_frame* ref, const me_frame* cur, const me_params* params,
+                            const float* net_out, int16_t* mv, int32_t* sad, uint8_t* fallback, void* stream);
+
+/*
  * Proposal network (learned-proposal mode; this library's addition, see
  * me_refine).  Input: for a frame pair of H x W Bayer samples (H, W divisible
  * by 4), the 2x2 means of the four packed planes of the reference (channels

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libme.so")
 SOURCES = ["api.cpp", "cnn_api.cpp", "prnet_api.cpp", "sad_search.hip", "warp.hip", "util.hip", "refine.hip",
-           "cnn.hip", "prnet.hip", "stats.hip"]
+           "cnn.hip", "prnet.hip", "stats.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 CFLAGS = ["-x", "hip", "--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17", "-Wall",

@@ -244,6 +244,9 @@ me_status me_ctx_create(int32_t device, me_ctx* out)
     hipError_t e = hipGetDeviceCount(&n);
     if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
     if (device < 0 || device >= n) return fail(ME_E_INVAL, "me_ctx_create: device %d not in [0, %d)", device, n);
+    // the device address of me_refine_noalloc's fixed scratch, once per device
+    me_status s = noalloc_resolve(device);
+    if (s != ME_OK) return s;
     me_ctx c = new (std::nothrow) me_ctx_s;
     if (!c) return fail(ME_E_NOMEM, "me_ctx_create: out of host memory");
     c->device = device;

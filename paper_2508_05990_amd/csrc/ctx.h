@@ -117,6 +117,9 @@ me_status check_refine_params(const me_params& p);
 // Refine + fallback on a network output already in device memory.
 me_status refine_impl(me_ctx ctx, const me_frame* ref, const me_frame* cur, const me_params& p, const float* net_out,
                       int16_t* mv, int32_t* sad, uint8_t* fallback, hipStream_t st);
+// Resolve, with `device` made current for the call, the device address of
+// the fixed scratch array of me_refine_noalloc (once per device).
+me_status noalloc_resolve(int device);
 // Pool + forward of one pair into ctx->cnn.out (proposal mode).
 me_status cnn_propose(me_ctx ctx, const me_frame* ref, const me_frame* cur, hipStream_t st);
 }  // namespace me

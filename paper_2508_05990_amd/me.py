@@ -77,6 +77,8 @@ _me_warp_features = _sig("me_warp_features", [_P, _P, _P, _I32, _I32, _I32, _I32
 _me_batch_submit = _sig("me_batch_submit", [_P, ctypes.POINTER(MeJob), _I32, _P])
 _me_refine = _sig("me_refine", [_P, ctypes.POINTER(MeFrame), ctypes.POINTER(MeFrame), ctypes.POINTER(MeParams), _P, _P,
                                 _P, _P, _P])
+_me_refine_noalloc = _sig("me_refine_noalloc", [_P, ctypes.POINTER(MeFrame), ctypes.POINTER(MeFrame),
+                                                ctypes.POINTER(MeParams), _P, _P, _P, _P, _P])
 _F = ctypes.c_float
 _me_autotune = _sig("me_autotune", [_P, ctypes.POINTER(MeFrame), ctypes.POINTER(MeFrame), _I32, _I32, _I32, _P, _P])
 _me_tuned_shape = _sig("me_tuned_shape", [_P, _I32, _I32, _I32, _I32, _P, _P])
@@ -136,7 +138,7 @@ EXPORTS = ["me_default_params", "me_ctx_create", "me_ctx_destroy", "me_estimate"
            "me_default_pyramid", "me_compose_vectors", "me_estimate_warp", "me_prnet_num_params", "me_prnet_create", "me_prnet_destroy",
            "me_prnet_set_params", "me_prnet_get_params", "me_prnet_forward", "me_prnet_train_step",
            "me_prnet_dw_forward", "me_prnet_dw_backward", "me_prnet_pw_forward", "me_prnet_pw_backward",
-           "me_prnet_loss", "me_sync", "me_sad_median", "me_fallback_weight"]
+           "me_prnet_loss", "me_sync", "me_sad_median", "me_fallback_weight", "me_refine_noalloc"]
 ME_NHWC, ME_NCHW = 0, 1
 ME_CNN_NPARAMS = 21699
 
@@ -306,9 +308,10 @@ def pyramid(ref, cur, ctx: Context, cfg: MePyramidCfg | None = None, mv=None, sa
 
 
 def refine(ref, cur, net_out, ctx: Context, block=16, radius=32, refine_radius=2, conf_logit_thresh=0.0,
-           sad_ratio=1.5, sad_median_per_sample=0.0, mv=None, sad=None, fallback=None, stream=None):
+           sad_ratio=1.5, sad_median_per_sample=0.0, mv=None, sad=None, fallback=None, stream=None, noalloc=False):
     """Learned-proposal refine + fallback given the network output [3, bh, bw] float32.
-    Returns (mv, sad, fallback)."""
+    Returns (mv, sad, fallback).  noalloc: call me_refine_noalloc (the step's
+    scratch in the library's fixed device array instead of context buffers)."""
     H, W = cur.shape
     bh, bw = block_grid(H, W, block)
     if tuple(net_out.shape) != (3, bh, bw) or net_out.dtype != torch.float32 or not net_out.is_contiguous():
@@ -322,8 +325,9 @@ def refine(ref, cur, net_out, ctx: Context, block=16, radius=32, refine_radius=2
     if fallback is None:
         fallback = torch.empty((bh, bw), dtype=torch.uint8, device=cur.device)
     fr, fc = frame_of(ref), frame_of(cur)
-    _check(_me_refine(ctx.handle, ctypes.byref(fr), ctypes.byref(fc), ctypes.byref(p), net_out.data_ptr(),
-                      mv.data_ptr(), sad.data_ptr(), fallback.data_ptr(), _stream_handle(stream)))
+    fn = _me_refine_noalloc if noalloc else _me_refine
+    _check(fn(ctx.handle, ctypes.byref(fr), ctypes.byref(fc), ctypes.byref(p), net_out.data_ptr(),
+              mv.data_ptr(), sad.data_ptr(), fallback.data_ptr(), _stream_handle(stream)))
     return mv, sad, fallback
 
 

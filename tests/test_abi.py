@@ -190,6 +190,26 @@ def test_refine_validation(me):
     assert args(ctypes.c_void_p(FAKE), FAKE) == 1
 
 
+def test_refine_noalloc_validation(me):
+    """The no-allocation refine checks its fixed scratch limit before it looks
+    at the context, so the limit is checked here without a GPU."""
+    p = me.make_params(8, 8, me.ME_MODE_PROPOSAL)
+    call = lambda ctx, f, net: me._me_refine_noalloc(ctx, ctypes.byref(f), ctypes.byref(f), ctypes.byref(p), net,
+                                                     FAKE, FAKE, None, None)
+    # 4104 x 4096 Bayer at B=8: 257 x 256 = 65,792 blocks > 65,536
+    big = _frame(me, 4104, 4096)
+    assert call(None, big, FAKE) == 1
+    assert b"exceed" in me._me_last_error()
+    # 4096 x 4096: exactly 65,536 blocks passes the limit and stops at the null context
+    edge = _frame(me, 4096, 4096)
+    assert call(None, edge, FAKE) == 1
+    assert b"null context" in me._me_last_error()
+    f = _frame(me)
+    assert call(ctypes.c_void_p(FAKE), f, 0) == 1      # null network output
+    p.refine_radius = 9
+    assert call(ctypes.c_void_p(FAKE), f, FAKE) == 1
+
+
 def test_prnet_num_params_and_validation(me):
     from oracle import prnet as P
 
