@@ -340,16 +340,19 @@ typedef struct {
  * and radii (the paper's batched grid over (Batch, h, w), Sec. 4.1 CUDA
  * settings, extended to uneven jobs).  jobs is a HOST array of n entries
  * (read before return); results are bit-identical to n separate me_estimate
- * calls.  Jobs of equal shape (block, radius, frame size, pitches) share one
- * launch of the full-search kernel over a (job, block row, block group) grid,
- * with the launch shape me_estimate would use for that shape (autotuned ones
- * included); the launches of all shapes, in order of first appearance, are
- * captured once as one HIP graph and replayed while the job shapes repeat.
- * Each workgroup reads its pair's pointers from a context-owned device table
- * that each submission restages through pinned memory.  Submissions that use
- * one context share that table: on one stream they are ordered; across
- * streams the caller must order them (or use one context per stream).
- * Returns ME_E_UNSUPPORTED for jobs other than exhaustive step 1.
+ * calls.  All jobs of one block size go through ONE persistent launch: a
+ * workgroup per resident slot repeatedly takes the next item -- a run of
+ * horizontally adjacent full-width blocks of one job, with that job's own
+ * radius, frame size and window plan -- from a device ticket counter until
+ * none is left; jobs are ordered by decreasing work per item.  Blocks cut by
+ * the right frame edge (frame width not a multiple of the block) are searched
+ * by an extra launch per job shape.  The launches are captured once as one HIP
+ * graph and replayed while the job shapes (block, radius, size, pitches, in
+ * order) repeat; each submission restages the pairs' pointers into
+ * context-owned device tables through pinned memory.  Submissions that use
+ * one context share those tables and the ticket counters: on one stream they
+ * are ordered; across streams the caller must order them (or use one context
+ * per stream).  Returns ME_E_UNSUPPORTED for jobs other than exhaustive step 1.
  */
 me_status me_batch_submit(me_ctx ctx, const me_job* jobs, int32_t n, void* stream);
 
@@ -370,7 +373,10 @@ me_status me_autotune(me_ctx ctx, const me_frame* ref, const me_frame* cur, int3
  * me_tuned_shape -- the launch shape the context uses for a full search with
  * (block, radius) on height x width Bayer frames (batch grid of Sec. 4.1):
  * shape[0] candidates per lane along x, shape[1] along y, shape[2] blocks per
- * workgroup, shape[3] the LDS window size in KB (rounded up).  *tuned (may be
+ * workgroup, shape[3] the LDS window size in KB (rounded up), shape[4] where the
+ * kernel reads the current block from: 0 scalar loads, 1 LDS (staged beside
+ * the window), shape[5] waves per block (2, 4 or 8; blocks x waves <= 8).
+ * shape holds 6 entries.  *tuned (may be
  * NULL) is 1 when the shape was recorded by me_autotune or
  * me_set_tuned_shape, 0 when it is the built-in default.  Host call, no GPU
  * work.  ME_E_INVAL on a null pointer, odd or empty frame or radius outside
@@ -378,12 +384,14 @@ me_status me_autotune(me_ctx ctx, const me_frame* ref, const me_frame* cur, int3
  *
  * me_set_tuned_shape -- record a shape in that form (for instance one that
  * me_tuned_shape reported in an earlier process, so that tuning persists):
- * shape[3] is the LDS budget in KB; the window band is the largest that fits
+ * shape[3] is the LDS budget in KB (window and, with shape[4] = 1, the staged
+ * current blocks); the window band is the largest that fits
  * it, so a reported shape set back gives the same launch.  Results do not
- * depend on the shape.  ME_E_UNSUPPORTED when the tile is not compiled for
- * the block size, blocks per workgroup is not 1 (or 2 with radius % 4 == 0),
- * or no band fits the budget (at most 158 KB); the stored table is unchanged
- * then.  Drops a batch graph captured earlier in the context, synchronising
+ * depend on the shape.  ME_E_INVAL when shape[4] is not 0 or 1 or shape[5]
+ * not 2, 4 or 8; ME_E_UNSUPPORTED when the tile is not compiled for the block
+ * size, blocks per workgroup x waves per block exceeds 8, more than one block
+ * per workgroup with radius % 4 != 0, or no band fits the budget (at most
+ * 158 KB); the stored table is unchanged then.  Drops a batch graph captured earlier in the context, synchronising
  * the device first.
  */
 me_status me_tuned_shape(me_ctx ctx, int32_t block, int32_t radius, int32_t height, int32_t width, int32_t* shape,

@@ -85,6 +85,7 @@ SearchArgs make_args(const me_frame* ref, const me_frame* cur, int B, int R, int
     a.step = 1;
     a.mv = mv;
     a.sad = sad;
+    a.wpb = 4;
     return a;
 }
 
@@ -103,6 +104,9 @@ me_ctx_s::~me_ctx_s()
     if (staged) (void)hipEventDestroy(staged);
     (void)hipFree(ptrs_dev);
     (void)hipHostFree(ptrs_host);
+    (void)hipFree(qjobs_dev);
+    (void)hipHostFree(qjobs_host);
+    (void)hipFree(qcount);
     (void)hipFree(pyr_mv[0]);
     (void)hipFree(pyr_mv[1]);
     (void)hipFree(pyr_sad);
@@ -545,8 +549,8 @@ me_status me_batch_submit(me_ctx ctx, const me_job* jobs, int32_t n, void* strea
     if (n == 0) return ME_OK;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
 
-    // shape of each job: pairs with equal (block, radius, size, pitches) share
-    // one launch over a (pair, block row, block group) grid
+    // shape of each job (block, radius, size, pitches): a submission whose
+    // shapes repeat the previous one's replays the captured graph
     std::vector<int64_t> shapes((size_t)n * 4);
     for (int32_t k = 0; k < n; ++k) {
         const me_job& j = jobs[k];
@@ -557,9 +561,31 @@ me_status me_batch_submit(me_ctx ctx, const me_job* jobs, int32_t n, void* strea
     }
     const bool same = ctx->graph && shapes == ctx->batch_shapes;
 
-    // groups in order of first appearance; slot[k] = row of job k in the table
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if (!ctx->staged) {
+        if ((e = hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming)) != hipSuccess ||
+            (e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(e, "me_batch_submit: setup");
+    }
+    if (!ctx->qcount) {
+        if (hipMalloc(&ctx->qcount, sizeof(int32_t) * kQueueCounters) != hipSuccess)
+            return fail(ME_E_NOMEM, "me_batch_submit: queue counters");
+        if ((e = launch_fill_i32(ctx->qcount, kQueueCounters, 0, st)) != hipSuccess)
+            return hip_fail(e, "me_batch_submit: queue counters");
+    }
+
+    // plan (new shapes only):
+    //  * full-width blocks: one persistent queue launch per block size over
+    //    all its jobs, jobs in decreasing order of work per item, tile shape of
+    //    the group's costliest job (tuned or default);
+    //  * blocks cut by the right frame edge: per-shape launches of the generic
+    //    kernel over a (job, block row) grid, pointers from a shape-grouped table.
     std::vector<int32_t> slot((size_t)n);
-    std::vector<std::pair<int32_t, int32_t>> groups;     // (first job, count)
+    std::vector<std::pair<int32_t, int32_t>> groups;     // partial-width shape groups: (first job, count)
+    std::vector<QueueJob> qplan;
+    std::vector<int32_t> qrow_job;
+    std::vector<QueueLaunch> qlaunch;
     if (same) {
         slot = ctx->batch_slot;
     } else {
@@ -579,35 +605,130 @@ me_status me_batch_submit(me_ctx ctx, const me_job* jobs, int32_t n, void* strea
             groups.push_back({m[0], (int32_t)m.size()});
             for (int32_t k : m) slot[k] = row++;
         }
+        for (int B : {8, 16, 32, 64}) {
+            std::vector<int32_t> ks;
+            int32_t dom = -1;
+            double dom_cost = -1.0;
+            for (int32_t k = 0; k < n; ++k) {
+                const me_job& j = jobs[k];
+                if (j.params.block != B || (j.cur.width / 2) / B == 0) continue;
+                ks.push_back(k);
+                const double nc = 2.0 * j.params.radius + 1.0;
+                const double cost = (double)(j.cur.height / 2) * (j.cur.width / 2) * nc * nc;
+                if (cost > dom_cost) {
+                    dom_cost = cost;
+                    dom = k;
+                }
+            }
+            if (ks.empty()) continue;
+            // tile shape: the costliest job's tuned shape, else 4x2 tiles with
+            // scalar loads of the current block (the queue kernel's register
+            // count keeps four waves per SIMD with them)
+            const me_job& d = jobs[dom];
+            TileCfg tile{};
+            tile.kx = 4;
+            tile.ky = 2;
+            tile.rs = 1;
+            {
+                std::lock_guard<std::mutex> g(ctx->mu);
+                auto it = ctx->tuned.find(std::make_tuple(B, d.params.radius, d.cur.height / 2, d.cur.width / 2));
+                if (it != ctx->tuned.end() && queue_supported(B, it->second.kx, it->second.ky)) {
+                    tile.kx = it->second.kx;
+                    tile.ky = it->second.ky;
+                    tile.cl = it->second.cl;
+                }
+            }
+            QueueLaunch ql{};
+            ql.block = B;
+            ql.tile = tile;
+            ql.first = (int32_t)qplan.size();
+            std::vector<std::pair<double, int32_t>> order;   // (-work per item, job)
+            std::vector<QueueJob> plans((size_t)n);
+            for (int32_t k : ks) {
+                const me_job& j = jobs[k];
+                QueueJob& q = plans[k];
+                q = QueueJob{};
+                q.ref_pitch = j.ref.pitch / 2;
+                q.cur_pitch = j.cur.pitch / 2;
+                q.Hp = j.cur.height / 2;
+                q.Wp = j.cur.width / 2;
+                q.bh = (q.Hp + B - 1) / B;
+                q.bw = (q.Wp + B - 1) / B;
+                q.R = j.params.radius;
+                size_t bytes = 0;
+                if (!plan_queue_job(B, tile, kLdsQueue, &q, &bytes) && !plan_queue_job(B, tile, kLdsQueueMax, &q, &bytes))
+                    return fail(ME_E_UNSUPPORTED, "me_batch_submit: job %d: no window plan for block %d radius %d", k,
+                                B, q.R);
+                if (bytes > ql.lds_bytes) ql.lds_bytes = bytes;
+                const double nc = 2.0 * q.R + 1.0;
+                order.push_back({-(double)q.nb * nc * nc, k});
+            }
+            std::stable_sort(order.begin(), order.end(),
+                             [](const std::pair<double, int32_t>& a, const std::pair<double, int32_t>& b) {
+                                 return a.first < b.first;
+                             });
+            int64_t items = 0;
+            for (const auto& o : order) {
+                QueueJob q = plans[o.second];
+                q.item0 = (int32_t)items;
+                items += (int64_t)q.bh * q.groups;
+                if (items > 0x7fffffff) return fail(ME_E_UNSUPPORTED, "me_batch_submit: too many blocks");
+                qplan.push_back(q);
+                qrow_job.push_back(o.second);
+            }
+            ql.n_jobs = (int32_t)qplan.size() - ql.first;
+            ql.n_items = (int32_t)items;
+            ql.counter = (int32_t)qlaunch.size();
+            if (ql.counter >= kQueueCounters) return fail(ME_E_UNSUPPORTED, "me_batch_submit: too many block sizes");
+            qlaunch.push_back(ql);
+        }
     }
 
-    hipError_t e = hipSetDevice(ctx->device);
-    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-    if (!ctx->staged) {
-        if ((e = hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming)) != hipSuccess ||
-            (e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking)) != hipSuccess)
-            return hip_fail(e, "me_batch_submit: setup");
-    }
-    // the previous submission's staging copy must be done before reuse
+    // the previous submission's staging copies must be done before reuse
     if ((e = hipEventSynchronize(ctx->staged)) != hipSuccess) return hip_fail(e, "me_batch_submit: staging wait");
-    if ((size_t)n > ctx->cap_ptrs) {
-        // a larger table moves: wait for launches that may still read the old
-        // one, and drop the graph that captured its address
+    const size_t nq = same ? ctx->qplan.size() : qplan.size();
+    if ((size_t)n > ctx->cap_ptrs || nq > ctx->cap_q) {
+        // larger tables move: wait for launches that may still read the old
+        // ones, and drop the graph that captured their addresses
         if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "me_batch_submit: synchronize");
         if (ctx->graph) {
             (void)hipGraphExecDestroy(ctx->graph);
             ctx->graph = nullptr;
         }
         ctx->batch_shapes.clear();
-        (void)hipFree(ctx->ptrs_dev);
-        (void)hipHostFree(ctx->ptrs_host);
-        ctx->ptrs_dev = nullptr;
-        ctx->ptrs_host = nullptr;
-        ctx->cap_ptrs = 0;
-        if (hipMalloc(&ctx->ptrs_dev, sizeof(JobPtrs) * n) != hipSuccess ||
-            hipHostMalloc(&ctx->ptrs_host, sizeof(JobPtrs) * n) != hipSuccess)
-            return fail(ME_E_NOMEM, "me_batch_submit: pointer table allocation failed");
-        ctx->cap_ptrs = (size_t)n;
+        if ((size_t)n > ctx->cap_ptrs) {
+            (void)hipFree(ctx->ptrs_dev);
+            (void)hipHostFree(ctx->ptrs_host);
+            ctx->ptrs_dev = nullptr;
+            ctx->ptrs_host = nullptr;
+            ctx->cap_ptrs = 0;
+            if (hipMalloc(&ctx->ptrs_dev, sizeof(JobPtrs) * n) != hipSuccess ||
+                hipHostMalloc(&ctx->ptrs_host, sizeof(JobPtrs) * n) != hipSuccess)
+                return fail(ME_E_NOMEM, "me_batch_submit: pointer table allocation failed");
+            ctx->cap_ptrs = (size_t)n;
+        }
+        if (nq > ctx->cap_q) {
+            (void)hipFree(ctx->qjobs_dev);
+            (void)hipHostFree(ctx->qjobs_host);
+            ctx->qjobs_dev = nullptr;
+            ctx->qjobs_host = nullptr;
+            ctx->cap_q = 0;
+            if (hipMalloc(&ctx->qjobs_dev, sizeof(QueueJob) * nq) != hipSuccess ||
+                hipHostMalloc(&ctx->qjobs_host, sizeof(QueueJob) * nq) != hipSuccess)
+                return fail(ME_E_NOMEM, "me_batch_submit: queue table allocation failed");
+            ctx->cap_q = nq;
+        }
+    }
+    if (!same) {
+        // a new plan: its tables are staged below and its launches captured
+        if (ctx->graph) {
+            (void)hipGraphExecDestroy(ctx->graph);
+            ctx->graph = nullptr;
+        }
+        ctx->batch_shapes.clear();
+        ctx->qplan.swap(qplan);
+        ctx->qrow_job.swap(qrow_job);
+        ctx->qlaunch.swap(qlaunch);
     }
     for (int32_t k = 0; k < n; ++k) {
         const me_job& j = jobs[k];
@@ -617,24 +738,30 @@ me_status me_batch_submit(me_ctx ctx, const me_job* jobs, int32_t n, void* strea
         p.mv = j.mv;
         p.sad = j.sad;
     }
+    for (size_t r = 0; r < nq; ++r) {
+        const me_job& j = jobs[ctx->qrow_job[r]];
+        QueueJob q = ctx->qplan[r];
+        q.ref = reinterpret_cast<const uint32_t*>(j.ref.data);
+        q.cur = reinterpret_cast<const uint32_t*>(j.cur.data);
+        q.mv = j.mv;
+        q.sad = j.sad;
+        ctx->qjobs_host[r] = q;
+    }
     if ((e = hipMemcpyAsync(ctx->ptrs_dev, ctx->ptrs_host, sizeof(JobPtrs) * n, hipMemcpyHostToDevice, st)) !=
             hipSuccess ||
+        (nq > 0 && (e = hipMemcpyAsync(ctx->qjobs_dev, ctx->qjobs_host, sizeof(QueueJob) * nq,
+                                       hipMemcpyHostToDevice, st)) != hipSuccess) ||
         (e = hipEventRecord(ctx->staged, st)) != hipSuccess)
         return hip_fail(e, "me_batch_submit: staging copy");
 
-    // one captured graph of the per-shape launches (the same kernels and
-    // launch shapes as single-pair calls, autotuned ones included); they read
-    // the pointer table at a fixed address, so a replay picks up new pairs
+    // one captured graph of the queue launches and the generic launches; they
+    // read the tables at fixed addresses, so a replay picks up new pairs
     if (!same) {
-        if (ctx->graph) {
-            (void)hipGraphExecDestroy(ctx->graph);
-            ctx->graph = nullptr;
-        }
-        ctx->batch_shapes.clear();
         std::vector<SearchArgs> args;
         std::vector<TileCfg> cfgs;
         for (const std::pair<int32_t, int32_t>& g : groups) {
             const me_job& j = jobs[g.first];
+            if ((j.cur.width / 2) % j.params.block == 0) continue;      // no block cut by the right edge
             SearchArgs a = make_args(&j.ref, &j.cur, j.params.block, j.params.radius, j.params.radius, nullptr,
                                      j.mv, j.sad);
             a.jobs = ctx->ptrs_dev + slot[g.first];
@@ -646,8 +773,17 @@ me_status me_batch_submit(me_ctx ctx, const me_job* jobs, int32_t n, void* strea
         if ((e = hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
             return hip_fail(e, "me_batch_submit: capture");
         hipError_t le = hipSuccess;
+        for (size_t i = 0; i < ctx->qlaunch.size() && le == hipSuccess; ++i) {
+            const QueueLaunch& ql = ctx->qlaunch[i];
+            QueueArgs q{};
+            q.jobs = ctx->qjobs_dev + ql.first;
+            q.n_jobs = ql.n_jobs;
+            q.n_items = ql.n_items;
+            q.counter = ctx->qcount + ql.counter;
+            le = launch_sad_queue(q, ql.block, ql.tile, ql.lds_bytes, ctx->capture_stream);
+        }
         for (size_t i = 0; i < args.size() && le == hipSuccess; ++i)
-            le = launch_sad_search(args[i], cfgs[i], 0, ctx->capture_stream);
+            le = launch_sad_search(args[i], cfgs[i], 0, ctx->capture_stream, 2);
         e = hipStreamEndCapture(ctx->capture_stream, &gr);
         if (le != hipSuccess) {
             if (gr) (void)hipGraphDestroy(gr);
@@ -771,22 +907,28 @@ me_status me_autotune(me_ctx ctx, const me_frame* ref, const me_frame* cur, int3
     const int shapes[6][2] = {{4, 4}, {8, 2}, {4, 2}, {8, 4}, {8, 1}, {4, 1}};
     const size_t caps[3] = {53 * 1024, 80 * 1024, 158 * 1024};
     std::vector<TileCfg> cands;
+    const int groupings[4][2] = {{1, 4}, {2, 4}, {2, 2}, {4, 2}};   // (blocks, waves per block)
     for (auto& sh : shapes)
-        for (int nb : {1, 2}) {
-            if (nb > 1 && radius % 4) continue;
-            for (size_t cap : caps) {
-                TileCfg c{};
-                c.kx = sh[0];
-                c.ky = sh[1];
-                c.nb = nb;
-                if (!tiles_supported(block, c.kx, c.ky) || !plan_tiles(block, radius, cap, &c)) continue;
-                bool dup = false;
-                for (const TileCfg& o : cands)
-                    dup |= o.kx == c.kx && o.ky == c.ky && o.nb == c.nb && o.band_ty == c.band_ty &&
-                           o.lds_pitch == c.lds_pitch;
-                if (!dup) cands.push_back(c);
+        for (auto& gp : groupings)
+            for (int cl : {0, 1}) {
+                const int nb = gp[0];
+                if (nb > 1 && radius % 4) continue;
+                for (size_t cap : caps) {
+                    TileCfg c{};
+                    c.kx = sh[0];
+                    c.ky = sh[1];
+                    c.nb = nb;
+                    c.wpb = gp[1];
+                    c.cl = cl;
+                    c.rs = 1;
+                    if (!tiles_supported(block, c.kx, c.ky) || !plan_tiles(block, radius, cap, &c)) continue;
+                    bool dup = false;
+                    for (const TileCfg& o : cands)
+                        dup |= o.kx == c.kx && o.ky == c.ky && o.nb == c.nb && o.band_ty == c.band_ty &&
+                               o.lds_pitch == c.lds_pitch && o.cl == c.cl && o.wpb == c.wpb;
+                    if (!dup) cands.push_back(c);
+                }
             }
-        }
     hipEvent_t t0, t1;
     if ((e = hipEventCreate(&t0)) != hipSuccess || (e = hipEventCreate(&t1)) != hipSuccess)
         return hip_fail(e, "me_autotune: events");
@@ -839,6 +981,8 @@ me_status me_tuned_shape(me_ctx ctx, int32_t block, int32_t radius, int32_t heig
     shape[1] = c.ky;
     shape[2] = c.nb;
     shape[3] = (int32_t)((c.lds_bytes + 1023) / 1024);
+    shape[4] = c.cl;
+    shape[5] = c.wpb ? c.wpb : 4;
     if (tuned) *tuned = found ? 1 : 0;
     return ME_OK;
 }
@@ -855,11 +999,19 @@ me_status me_set_tuned_shape(me_ctx ctx, int32_t block, int32_t radius, int32_t 
     c.kx = shape[0];
     c.ky = shape[1];
     c.nb = shape[2];
+    c.cl = shape[4];
+    c.wpb = shape[5];
+    c.rs = 1;
+    if (c.cl != 0 && c.cl != 1)
+        return fail(ME_E_INVAL, "me_set_tuned_shape: current-block source %d not 0 or 1", c.cl);
+    if (c.wpb != 2 && c.wpb != 4 && c.wpb != 8)
+        return fail(ME_E_INVAL, "me_set_tuned_shape: %d waves per block (2, 4 or 8)", c.wpb);
     if (!tiles_supported(block, c.kx, c.ky))
         return fail(ME_E_UNSUPPORTED, "me_set_tuned_shape: tile %dx%d not compiled for block %d", c.kx, c.ky, block);
-    if (c.nb < 1 || c.nb > 2 || (c.nb > 1 && radius % 4))
-        return fail(ME_E_UNSUPPORTED, "me_set_tuned_shape: %d blocks per workgroup (1, or 2 when radius %% 4 == 0)",
-                    c.nb);
+    if (c.nb < 1 || c.nb * c.wpb > 8 || (c.nb > 1 && radius % 4))
+        return fail(ME_E_UNSUPPORTED,
+                    "me_set_tuned_shape: %d blocks of %d waves per workgroup (at most 8 waves; one block unless "
+                    "radius %% 4 == 0)", c.nb, c.wpb);
     if (shape[3] < 1 || shape[3] > 158 || !plan_tiles(block, radius, (size_t)shape[3] * 1024, &c))
         return fail(ME_E_UNSUPPORTED, "me_set_tuned_shape: no window band fits in %d KB of LDS (at most 158)",
                     shape[3]);

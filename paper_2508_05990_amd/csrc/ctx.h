@@ -24,6 +24,18 @@ SearchArgs make_args(const me_frame* ref, const me_frame* cur, int B, int R, int
 // Proposal-network state: float32 master parameters, AdamW moments, the
 // bfloat16 operand packings, and activation/gradient buffers sized for the
 // largest batch seen so far.
+// One queue launch of a batch plan: block size, tile shape, LDS bytes, its
+// rows [first, first + n_jobs) of the queue table, item count and counter.
+struct QueueLaunch {
+    int block;
+    TileCfg tile;
+    size_t lds_bytes;
+    int32_t first, n_jobs, n_items, counter;
+};
+constexpr int kQueueCounters = 8;
+constexpr size_t kLdsQueue = 80 * 1024;      // two 8-wave workgroups per CU
+constexpr size_t kLdsQueueMax = 158 * 1024;
+
 struct CnnState {
     bool loaded = false;
     float* params = nullptr;
@@ -79,6 +91,17 @@ struct me_ctx_s {
     hipGraphExec_t graph = nullptr;
     std::vector<int64_t> batch_shapes;
     std::vector<int32_t> batch_slot;     // job k -> its row in the pointer table
+    // queue launches of the batch plan: per-job geometry in launch order (the
+    // job index of each row; pointers filled at each submission), the device
+    // table and its pinned staging, the launches, and their ticket counters
+    // (zero between launches)
+    std::vector<me::QueueJob> qplan;
+    std::vector<int32_t> qrow_job;
+    std::vector<me::QueueLaunch> qlaunch;
+    me::QueueJob* qjobs_dev = nullptr;
+    me::QueueJob* qjobs_host = nullptr;
+    size_t cap_q = 0;
+    int32_t* qcount = nullptr;
     // pyramid search: vectors of the intermediate stages (ping-pong) and SADs
     int16_t* pyr_mv[2] = {nullptr, nullptr};
     int32_t* pyr_sad = nullptr;

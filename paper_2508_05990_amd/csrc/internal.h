@@ -20,6 +20,33 @@ struct JobPtrs {
 // packed-plane pixel column k of the two planes that live on row r's parity.
 // A packed displacement (dx, dy) is then a displacement of dx words and 2*dy
 // mosaic rows.
+// One frame pair of a queue launch (batch submission): its pointers, geometry,
+// radius and window plan.  A launch's items are the (block row, block group)
+// pairs of every job's full-width blocks, job after job; item0 is the job's
+// first item.
+struct QueueJob {
+    const uint32_t* ref;
+    const uint32_t* cur;
+    int16_t* mv;
+    int32_t* sad;
+    int64_t ref_pitch, cur_pitch;   // words per mosaic row
+    int32_t Hp, Wp, bh, bw;
+    int32_t R;
+    int32_t nb, wpb;                // blocks per item, waves per block
+    int32_t band_ty, lds_pitch, cur_lds;
+    int32_t cols;                   // full-width block columns
+    int32_t groups;                 // items per block row, ceil(cols / nb)
+    int32_t item0;
+    int32_t rs;                     // remainder rows as single candidates
+};
+
+struct QueueArgs {
+    const QueueJob* jobs;           // device table, ordered by item0
+    int32_t n_jobs;
+    int32_t n_items;
+    int32_t* counter;               // zero at launch; the launch leaves it zero
+};
+
 struct SearchArgs {
     const uint32_t* ref;
     const uint32_t* cur;
@@ -42,6 +69,9 @@ struct SearchArgs {
     int32_t lds_pitch;      // words per LDS window row (multiple of 4)
     int32_t col0, ncols;    // block columns covered by a launch without a list
     int32_t nb;             // horizontally adjacent blocks per workgroup (1 with a list or predictors)
+    int32_t cur_lds;        // LDS word offset of the staged current blocks (shapes with cl = 1)
+    int32_t wpb;            // waves per block of the tiled kernel (nb * wpb waves per workgroup)
+    int32_t rs;             // remainder rows as single candidates (TileCfg::rs)
     // batch launch: n_jobs pairs of this shape (block, radius, frame size,
     // pitches); each workgroup takes ref/cur/mv/sad of its pair from jobs[]
     // instead of the fields above.  Null for a single pair.
@@ -70,6 +100,9 @@ struct TileCfg {
     int band_ty;   // tile rows per LDS band
     int lds_pitch; // words per LDS row
     size_t lds_bytes;
+    int cl;        // 1: current blocks staged in LDS (after the window); 0: read through scalar loads
+    int wpb;       // waves per block: 2, 4 or 8 (0 = 4)
+    int rs;        // 1: candidate rows below the main tiles as single candidates (else KX x 1 tiles)
 };
 
 // Fill in the LDS geometry of `cfg` (kx, ky, nb set) for block size B and
@@ -92,7 +125,18 @@ bool small_search(int B, int R);
 
 // Full or stage search of one pair, of a.n_jobs pairs of one shape
 // (a.jobs), or of the first *a.list_n blocks of a.list (n_wg = list capacity).
-hipError_t launch_sad_search(const SearchArgs& a, const TileCfg& cfg, int n_wg, hipStream_t stream);
+// parts: 1 = full-width blocks (tiled kernel), 2 = blocks cut by the right
+// frame edge (generic kernel), 3 = both.
+hipError_t launch_sad_search(const SearchArgs& a, const TileCfg& cfg, int n_wg, hipStream_t stream, int parts = 3);
+
+// Queue launches (batch submission): tile shapes with a queue kernel; the
+// plan of one job for the launch's tile (kx, ky, cl) within lds_cap bytes
+// (fills nb, wpb, band_ty, lds_pitch, cur_lds, cols, groups; the caller sets
+// item0), and the launch over all jobs of one block size (lds_bytes: the
+// largest job plan).
+bool queue_supported(int B, int kx, int ky);
+bool plan_queue_job(int B, const TileCfg& tile, size_t lds_cap, QueueJob* j, size_t* lds_bytes);
+hipError_t launch_sad_queue(const QueueArgs& q, int B, const TileCfg& tile, size_t lds_bytes, hipStream_t stream);
 
 // Chained block vectors over a group of pictures (out may alias ms).
 hipError_t launch_compose(const int16_t* ms, const int16_t* ma, int16_t* out, int bh, int bw, int B, int Hp, int Wp,

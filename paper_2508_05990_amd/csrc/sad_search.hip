@@ -27,7 +27,7 @@ constexpr int kMaxWaves = 16;
 // Workgroup size limit the tiled kernel is compiled for (__launch_bounds__):
 // at most two blocks (8 waves) per workgroup.
 constexpr int kTiledMaxThreads = 512;
-constexpr int kWavesPerBlock = 4;
+constexpr int kWavesPerBlock = 4;         // default waves per block (a launch may use 2 or 8)
 constexpr int kMaxPitch = 256;            // words per LDS row (four 64-word chunks)
 
 // The current frame is read-only for the whole launch and every read of it is
@@ -214,6 +214,94 @@ __device__ __forceinline__ void tile_sads(cptr_t curp, int64_t cur_pitch, int h,
     }
 }
 
+// The same tile walk with the current block staged in LDS (rows of B words)
+// and read as a broadcast (every lane the same address) into VGPRs: the loop
+// then issues only LDS reads, which complete in order, so each wait covers
+// exactly the reads it needs (no scalar load in flight behind it).  Per step,
+// the ring slot for the tile's last candidate row and the next block row are
+// requested first, the candidate rows whose LDS rows are already held are
+// summed, and only then does the wave wait for the new slot.
+template <int CW, int NCH, int KX, int KY>
+__device__ __forceinline__ void tile_sads_cl(const uint4* __restrict__ cur4, int h, const uint4* __restrict__ lbase4,
+                                             int pitch4, uint32_t (&acc)[KY][KX])
+{
+    constexpr int B = CW * NCH;
+    constexpr int SEGV = (CW + KX - 1 + 3) / 4;
+    constexpr int CV = CW / 4;                       // uint4 per row chunk of the current block
+    constexpr int RP = B / 4;                        // uint4 per current-block row
+    constexpr int KY2 = KY % 2 == 0 ? KY : 2 * KY;   // steps per unrolled group (even)
+#pragma unroll
+    for (int j = 0; j < KY; ++j)
+#pragma unroll
+        for (int i = 0; i < KX; ++i) acc[j][i] = 0u;
+
+#pragma unroll 1
+    for (int q = 0; q < NCH; ++q) {
+#pragma unroll 1
+        for (int par = 0; par < 2; ++par) {
+            const uint4* col4 = lbase4 + par * pitch4 + (q * CW) / 4;   // LDS row par, chunk q
+            const uint4* crow = cur4 + par * RP + q * CV;                  // block row par, chunk q
+            uint4 ring[KY][SEGV];
+#pragma unroll
+            for (int t = 0; t < KY - 1; ++t)
+#pragma unroll
+                for (int v = 0; v < SEGV; ++v) ring[t][v] = col4[(2 * t) * pitch4 + v];
+            uint4 cA[CV], cB[CV];
+#pragma unroll
+            for (int v = 0; v < CV; ++v) cA[v] = crow[v];
+            // step st (u = st mod KY2): SADs against block row par + 2 st (cu);
+            // block row par + 2 (st + 1) into cx (the last step rereads its own row)
+            auto one = [&](const int u, const int st, const uint4(&cu)[CV], uint4(&cx)[CV]) {
+#pragma unroll
+                for (int v = 0; v < SEGV; ++v) ring[(u + KY - 1) % KY][v] = col4[(2 * (st + KY - 1)) * pitch4 + v];
+                const int nx = st + 1 < h ? st + 1 : st;
+#pragma unroll
+                for (int v = 0; v < CV; ++v) cx[v] = crow[(2 * nx) * RP + v];
+                uint32_t c[CW];
+#pragma unroll
+                for (int v = 0; v < CV; ++v) {
+                    c[4 * v + 0] = cu[v].x;
+                    c[4 * v + 1] = cu[v].y;
+                    c[4 * v + 2] = cu[v].z;
+                    c[4 * v + 3] = cu[v].w;
+                }
+#pragma unroll
+                for (int j = 0; j < KY; ++j) {
+                    uint32_t seg[SEGV * 4];
+#pragma unroll
+                    for (int v = 0; v < SEGV; ++v) {
+                        const uint4 t4 = ring[(u + j) % KY][v];
+                        seg[4 * v + 0] = t4.x;
+                        seg[4 * v + 1] = t4.y;
+                        seg[4 * v + 2] = t4.z;
+                        seg[4 * v + 3] = t4.w;
+                    }
+#pragma unroll
+                    for (int k = 0; k < CW; ++k)
+#pragma unroll
+                        for (int i = 0; i < KX; ++i) acc[j][i] = __builtin_amdgcn_sad_u16(c[k], seg[k + i], acc[j][i]);
+                }
+            };
+            int step = 0;
+#pragma unroll 1
+            for (; step + KY2 <= h; step += KY2) {
+#pragma unroll
+                for (int u = 0; u < KY2; ++u) {
+                    if (u & 1) one(u, step + u, cB, cA);
+                    else one(u, step + u, cA, cB);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < KY2 - 1; ++u) {              // h not a multiple of KY2
+                if (step + u < h) {
+                    if (u & 1) one(u, step + u, cB, cA);
+                    else one(u, step + u, cA, cB);
+                }
+            }
+        }
+    }
+}
+
 // One candidate per lane with a 16-byte aligned LDS column (b128 reads).
 template <int CW, int NCH>
 __device__ __forceinline__ uint32_t single_sad_aligned(cptr_t curp, int64_t cur_pitch, int rows2,
@@ -278,9 +366,10 @@ __device__ __forceinline__ uint32_t single_sad(cptr_t curp, int64_t cur_pitch, i
 // The block's waves take the tasks round-robin, starting at a wave that
 // rotates with the block index so the short extra tasks spread over SIMDs.
 // lds: LDS word of the block's candidate (dxlo, band row 0) for block row 0.
-template <int CW, int NCH, int KX, int KY>
+template <int CW, int NCH, int KX, int KY, bool CL>
 __device__ __forceinline__ void block_band(const SearchArgs& a, const BlockGeo& g, int y0c, int nyb, int wib,
-                                           const uint32_t* lds, int pitch, int lane, uint64_t& best)
+                                           const uint32_t* lds, int pitch, int lane, uint64_t& best,
+                                           const uint4* cur4)
 {
     const uint4* lds4 = reinterpret_cast<const uint4*>(lds);
     const int pitch4 = pitch >> 2;
@@ -289,22 +378,31 @@ __device__ __forceinline__ void block_band(const SearchArgs& a, const BlockGeo& 
     const int txr = (nx + KX - 1) / KX;
     const int tyn = nyb / KY, myb = tyn * KY, ryb = nyb - myb;
     const int n_main = txn * tyn;
-    const int n_rows = txr * ryb;
+    // remainder rows (below the main tiles): KX x 1 tiles, or with a.rs single
+    // candidates after the remainder columns (lanes spread more evenly over
+    // the block's waves when a tile row would give one wave a long extra task)
+    const int n_rows = a.rs ? 0 : txr * ryb;
     const int n_single = rx * myb;
+    const int n_single2 = a.rs ? ryb * nx : 0;
     const int t_main = (n_main + 63) >> 6;
     const int t_rows = t_main + ((n_rows + 63) >> 6);
-    const int tasks = t_rows + ((n_single + 63) >> 6);
+    const int t_single = t_rows + ((n_single + 63) >> 6);
+    const int tasks = t_single + ((n_single2 + 63) >> 6);
     cptr_t curp = as_const(a.cur + 2LL * g.y0 * a.cur_pitch + g.x0);
-    const int first = (wib + kWavesPerBlock - g.blk % kWavesPerBlock) % kWavesPerBlock;
-    for (int task = first; task < tasks; task += kWavesPerBlock) {
+    const int wpb = a.wpb;
+    const int first = (wib + wpb - g.blk % wpb) % wpb;
+    for (int task = first; task < tasks; task += wpb) {
         if (task < t_main) {
             const int t = task * 64 + lane;
             const bool active = t < n_main;
             const int tt = active ? t : task * 64;
             const int tyl = tt / txn, tx = tt - tyl * txn;
             uint32_t acc[KY][KX];
-            tile_sads<CW, NCH, KX, KY>(curp, a.cur_pitch, g.h, lds4 + (2 * tyl * KY) * pitch4 + (tx * KX) / 4, pitch4,
-                                       acc);
+            if (CL)
+                tile_sads_cl<CW, NCH, KX, KY>(cur4, g.h, lds4 + (2 * tyl * KY) * pitch4 + (tx * KX) / 4, pitch4, acc);
+            else
+                tile_sads<CW, NCH, KX, KY>(curp, a.cur_pitch, g.h, lds4 + (2 * tyl * KY) * pitch4 + (tx * KX) / 4,
+                                           pitch4, acc);
             if (active) {
 #pragma unroll
                 for (int j = 0; j < KY; ++j)
@@ -321,7 +419,10 @@ __device__ __forceinline__ void block_band(const SearchArgs& a, const BlockGeo& 
             const int ry = tt / txr, tx = tt - ry * txr;
             const int cy = myb + ry;
             uint32_t acc[1][KX];
-            tile_sads<CW, NCH, KX, 1>(curp, a.cur_pitch, g.h, lds4 + (2 * cy) * pitch4 + (tx * KX) / 4, pitch4, acc);
+            if (CL)
+                tile_sads_cl<CW, NCH, KX, 1>(cur4, g.h, lds4 + (2 * cy) * pitch4 + (tx * KX) / 4, pitch4, acc);
+            else
+                tile_sads<CW, NCH, KX, 1>(curp, a.cur_pitch, g.h, lds4 + (2 * cy) * pitch4 + (tx * KX) / 4, pitch4, acc);
             if (active) {
 #pragma unroll
                 for (int i = 0; i < KX; ++i) {
@@ -330,6 +431,16 @@ __device__ __forceinline__ void block_band(const SearchArgs& a, const BlockGeo& 
                         best = key < best ? key : best;
                     }
                 }
+            }
+        } else if (task >= t_single) {
+            const int t = (task - t_single) * 64 + lane;
+            const bool active = t < n_single2;
+            const int tt = active ? t : (task - t_single) * 64;
+            const int cy = myb + tt / nx, cx = tt - (tt / nx) * nx;
+            const uint32_t sad = single_sad_full<CW>(curp, a.cur_pitch, 2 * g.h, NCH, lds + 2 * cy * pitch + cx, pitch);
+            if (active) {
+                const uint64_t key = make_key(sad, g.dxlo + cx, g.dylo + y0c + cy);
+                best = key < best ? key : best;
             }
         } else {
             const int t = (task - t_rows) * 64 + lane;
@@ -432,7 +543,37 @@ __device__ __forceinline__ void warp_block(const SearchArgs& a, int blk, uint64_
     else warp_block_t<false>(a, blk, best, t, nt);
 }
 
-template <int CW, int NCH, int KX, int KY>
+// Stage the current frame's rows [2 y0, 2 y0 + 2h) x words [x0, x0 + B) of
+// the group's blocks into LDS at `dst` (block m at m * 2B * B words, rows of B
+// words), 64 consecutive LDS words per wave instruction; rows past 2h load
+// row 2h - 1 (never read).  The caller waits (vmcnt) and barriers.
+template <int B>
+__device__ __forceinline__ void stage_cur(const SearchArgs& a, uint32_t* dst, int y0, int x0, int h, int nblk, int wave,
+                                          int nw, int lane)
+{
+    constexpr int RPI = 64 / B;                      // rows per 64-word instruction
+    constexpr int CHUNKS = B > 64 ? B / 64 : 1;
+    constexpr int W = B < 64 ? B : 64;
+    const int rows = 2 * B;
+    const int per_blk = (rows / (B < 64 ? RPI : 1)) * CHUNKS;
+    for (int it = wave; it < nblk * per_blk; it += nw) {
+        const int m = it / per_blk, k = it - m * per_blk;
+        int r, c;
+        if (B < 64) {
+            r = k * RPI + lane / W;
+            c = lane % W;
+        } else {
+            r = k / CHUNKS;
+            c = (k % CHUNKS) * 64 + lane;
+        }
+        const int rr = min(r, 2 * h - 1);
+        const uint32_t* src = a.cur + (2LL * y0 + rr) * a.cur_pitch + x0 + m * B + c;
+        __builtin_amdgcn_global_load_lds(src, dst + m * rows * B + (B < 64 ? k * 64 : r * B + (k % CHUNKS) * 64),
+                                         4, 0, 0);
+    }
+}
+
+template <int CW, int NCH, int KX, int KY, bool CL>
 __device__ __forceinline__ void run_tiled(const SearchArgs& a, int first_blk, int nblk, uint32_t* lds, uint64_t* red)
 {
     constexpr int B = CW * NCH;
@@ -443,8 +584,9 @@ __device__ __forceinline__ void run_tiled(const SearchArgs& a, int first_blk, in
     const int pitch = a.lds_pitch;
     BlockGeo g0;
     block_geo(a, B, first_blk, g0);
-    const int mine = wave / kWavesPerBlock;         // this wave's block within the group
-    const int wib = wave - mine * kWavesPerBlock;
+    const int wpb = a.wpb;                          // waves per block
+    const int mine = wave / wpb;                    // this wave's block within the group
+    const int wib = wave - mine * wpb;
     const bool has_block = mine < nblk;
     BlockGeo g;
     block_geo(a, B, first_blk + (has_block ? mine : 0), g);
@@ -459,10 +601,12 @@ __device__ __forceinline__ void run_tiled(const SearchArgs& a, int first_blk, in
             const int nyb = min(band, ny - y0c);
             __syncthreads();
             stage_window(a, lds, 2LL * (g0.y0 + g0.dylo + y0c), left, 2 * (g0.h + nyb - 1), wave, nw, lane);
+            if (CL && y0c == 0) stage_cur<B>(a, lds + a.cur_lds, g0.y0, g0.x0, g0.h, nblk, wave, nw, lane);
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
             if (has_block && g.dxlo <= g.dxhi)
-                block_band<CW, NCH, KX, KY>(a, g, y0c, nyb, wib, lds + (g.x0 + g.dxlo - left), pitch, lane, best);
+                block_band<CW, NCH, KX, KY, CL>(a, g, y0c, nyb, wib, lds + (g.x0 + g.dxlo - left), pitch, lane, best,
+                                                reinterpret_cast<const uint4*>(lds + a.cur_lds + mine * 2 * B * B));
         }
     }
     best = wave_min_u64(best);
@@ -470,14 +614,14 @@ __device__ __forceinline__ void run_tiled(const SearchArgs& a, int first_blk, in
     __syncthreads();
     if (has_block && wib == 0 && lane == 0) {
         uint64_t b = red[wave];
-        for (int k = 1; k < kWavesPerBlock; ++k) b = red[wave + k] < b ? red[wave + k] : b;
+        for (int k = 1; k < wpb; ++k) b = red[wave + k] < b ? red[wave + k] : b;
         write_result(a, g.blk, b);
     }
     if (a.wz && has_block) {
-        const int w0 = mine * kWavesPerBlock;
+        const int w0 = mine * wpb;
         uint64_t b = red[w0];
-        for (int k = 1; k < kWavesPerBlock; ++k) b = red[w0 + k] < b ? red[w0 + k] : b;
-        warp_block(a, g.blk, b, wib * 64 + lane, kWavesPerBlock * 64);
+        for (int k = 1; k < wpb; ++k) b = red[w0 + k] < b ? red[w0 + k] : b;
+        warp_block(a, g.blk, b, wib * 64 + lane, wpb * 64);
     }
 }
 
@@ -543,7 +687,7 @@ __device__ __forceinline__ SearchArgs for_job(const SearchArgs& a, int job)
 // predictors are given, since their candidate rows then differ).  BATCH: the
 // grid covers a.n_jobs pairs of one shape, job-major (the paper's batch
 // dimension of the (Batch, h, w) grid).
-template <int CW, int NCH, int KX, int KY, bool BATCH>
+template <int CW, int NCH, int KX, int KY, bool BATCH, bool CL>
 __global__ __launch_bounds__(kTiledMaxThreads) void sad_search_kernel(SearchArgs a)
 {
     extern __shared__ uint4 lds_dyn[];
@@ -561,7 +705,7 @@ __global__ __launch_bounds__(kTiledMaxThreads) void sad_search_kernel(SearchArgs
         nblk = min(a.nb, a.ncols - c0);
         if (min(B, a.Wp - (first_blk % a.bw) * B) != B) return;
         const SearchArgs b = for_job(a, job);
-        run_tiled<CW, NCH, KX, KY>(b, first_blk, nblk, reinterpret_cast<uint32_t*>(lds_dyn), red);
+        run_tiled<CW, NCH, KX, KY, CL>(b, first_blk, nblk, reinterpret_cast<uint32_t*>(lds_dyn), red);
         return;
     }
     if (a.list) {
@@ -577,7 +721,71 @@ __global__ __launch_bounds__(kTiledMaxThreads) void sad_search_kernel(SearchArgs
         nblk = min(a.nb, a.ncols - c0);
     }
     if (min(B, a.Wp - (first_blk % a.bw) * B) != B) return;   // partial-width blocks: generic kernel
-    run_tiled<CW, NCH, KX, KY>(a, first_blk, nblk, reinterpret_cast<uint32_t*>(lds_dyn), red);
+    run_tiled<CW, NCH, KX, KY, CL>(a, first_blk, nblk, reinterpret_cast<uint32_t*>(lds_dyn), red);
+}
+
+// Persistent search over a queue of items from many frame pairs of one block
+// size (the paper's (Batch, h, w) grid with uneven jobs in one launch): each
+// workgroup repeatedly takes the next item -- a group of a job's horizontally
+// adjacent full-width blocks -- from a device counter and searches it with the
+// tiled code above, until the queue is empty.  Items are ordered by job
+// (costlier jobs first on the host side), so every workgroup stays busy until
+// the last items, whatever the mix of frame sizes and radii.  The workgroup
+// that draws the last ticket (n_items + gridDim.x - 1; every workgroup draws
+// exactly one past the end) sets the counter back to zero for the next launch.
+template <int CW, int NCH, int KX, int KY, bool CL>
+__global__ __launch_bounds__(kTiledMaxThreads) void sad_queue_kernel(QueueArgs q)
+{
+    extern __shared__ uint4 lds_dyn[];
+    __shared__ uint64_t red[kMaxWaves];
+    __shared__ int s_item;
+    constexpr int B = CW * NCH;
+    int item;
+    for (;;) {
+        __syncthreads();                              // previous item's window, keys and ticket are free
+        if (threadIdx.x == 0) s_item = atomicAdd(q.counter, 1);
+        __syncthreads();
+        item = __builtin_amdgcn_readfirstlane(s_item);
+        if (item >= q.n_items) break;
+        int lo = 0, hi = q.n_jobs - 1;                // last job whose first item is <= item
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (q.jobs[mid].item0 <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const QueueJob& j = q.jobs[lo];
+        SearchArgs a{};
+        a.ref = j.ref;
+        a.cur = j.cur;
+        a.ref_pitch = j.ref_pitch;
+        a.cur_pitch = j.cur_pitch;
+        a.block = B;
+        a.Hp = j.Hp;
+        a.Wp = j.Wp;
+        a.bh = j.bh;
+        a.bw = j.bw;
+        a.R = j.R;
+        a.limit = j.R;
+        a.pred_ratio = 1;
+        a.pred_bw = j.bw;
+        a.step = 1;
+        a.mv = j.mv;
+        a.sad = j.sad;
+        a.band_ty = j.band_ty;
+        a.lds_pitch = j.lds_pitch;
+        a.nb = j.nb;
+        a.wpb = j.wpb;
+        a.cur_lds = j.cur_lds;
+        a.rs = j.rs;
+        a.col0 = 0;
+        a.ncols = j.cols;
+        const int it = item - j.item0;
+        const int bi = it / j.groups, gj = it - bi * j.groups;
+        const int c0 = gj * j.nb;
+        run_tiled<CW, NCH, KX, KY, CL>(a, bi * j.bw + c0, min(j.nb, j.cols - c0), reinterpret_cast<uint32_t*>(lds_dyn),
+                                       red);
+    }
+    if (threadIdx.x == 0 && item == q.n_items + (int)gridDim.x - 1) atomicExch(q.counter, 0);
 }
 
 // Blocks cut by the right frame edge: one candidate per lane, runtime width.
@@ -825,28 +1033,34 @@ __global__ __launch_bounds__(256) void sad_step_kernel(SearchArgs a)
 
 using KernelFn = void (*)(SearchArgs);
 
-template <int CW, int NCH, bool BATCH>
+template <int CW, int NCH, bool BATCH, bool CL>
 KernelFn table_get(int kx, int ky)
 {
-    if (kx == 4 && ky == 1) return sad_search_kernel<CW, NCH, 4, 1, BATCH>;
-    if (kx == 4 && ky == 2) return sad_search_kernel<CW, NCH, 4, 2, BATCH>;
-    if (kx == 4 && ky == 4) return sad_search_kernel<CW, NCH, 4, 4, BATCH>;
-    if (kx == 8 && ky == 1) return sad_search_kernel<CW, NCH, 8, 1, BATCH>;
-    if (kx == 8 && ky == 2) return sad_search_kernel<CW, NCH, 8, 2, BATCH>;
-    if (kx == 8 && ky == 4) return sad_search_kernel<CW, NCH, 8, 4, BATCH>;
+    if (kx == 4 && ky == 1) return sad_search_kernel<CW, NCH, 4, 1, BATCH, CL>;
+    if (kx == 4 && ky == 2) return sad_search_kernel<CW, NCH, 4, 2, BATCH, CL>;
+    if (kx == 4 && ky == 4) return sad_search_kernel<CW, NCH, 4, 4, BATCH, CL>;
+    if (kx == 8 && ky == 1) return sad_search_kernel<CW, NCH, 8, 1, BATCH, CL>;
+    if (kx == 8 && ky == 2) return sad_search_kernel<CW, NCH, 8, 2, BATCH, CL>;
+    if (kx == 8 && ky == 4) return sad_search_kernel<CW, NCH, 8, 4, BATCH, CL>;
     return nullptr;
 }
 
-template <bool BATCH>
-KernelFn kernel_for(int B, int kx, int ky)
+template <bool BATCH, bool CL>
+KernelFn kernel_for_cl(int B, int kx, int ky)
 {
     switch (B) {
-    case 8: return table_get<8, 1, BATCH>(kx, ky);
-    case 16: return table_get<16, 1, BATCH>(kx, ky);
-    case 32: return table_get<16, 2, BATCH>(kx, ky);
-    case 64: return table_get<16, 4, BATCH>(kx, ky);
+    case 8: return table_get<8, 1, BATCH, CL>(kx, ky);
+    case 16: return table_get<16, 1, BATCH, CL>(kx, ky);
+    case 32: return table_get<16, 2, BATCH, CL>(kx, ky);
+    case 64: return table_get<16, 4, BATCH, CL>(kx, ky);
     default: return nullptr;
     }
+}
+
+template <bool BATCH>
+KernelFn kernel_for(int B, int kx, int ky, int cl)
+{
+    return cl ? kernel_for_cl<BATCH, true>(B, kx, ky) : kernel_for_cl<BATCH, false>(B, kx, ky);
 }
 
 constexpr size_t kLdsCap = 53 * 1024;    // preferred: 3 workgroups per CU
@@ -886,19 +1100,63 @@ size_t tiled_bytes(int B, int n, int ky, int band_ty, int pitch)
     return (size_t)2 * (B + rows - 1) * pitch * 4;
 }
 
+// LDS bytes of the staged current blocks (2B rows of B words per block).
+size_t cur_bytes(int B, int nb, int cl) { return cl ? (size_t)nb * 2 * B * B * 4 : 0; }
+
 }  // namespace
 
-bool tiles_supported(int B, int kx, int ky) { return kernel_for<false>(B, kx, ky) != nullptr; }
+bool tiles_supported(int B, int kx, int ky) { return kernel_for<false>(B, kx, ky, 0) != nullptr; }
+
+namespace {
+
+using QueueFn = void (*)(QueueArgs);
+
+template <int CW, int NCH, bool CL>
+QueueFn queue_get(int kx, int ky)
+{
+    if (kx == 4 && ky == 1) return sad_queue_kernel<CW, NCH, 4, 1, CL>;
+    if (kx == 4 && ky == 2) return sad_queue_kernel<CW, NCH, 4, 2, CL>;
+    if (kx == 4 && ky == 4) return sad_queue_kernel<CW, NCH, 4, 4, CL>;
+    if (kx == 8 && ky == 2) return sad_queue_kernel<CW, NCH, 8, 2, CL>;
+    if (kx == 8 && ky == 4) return sad_queue_kernel<CW, NCH, 8, 4, CL>;
+    return nullptr;
+}
+
+template <bool CL>
+QueueFn queue_kernel_for_cl(int B, int kx, int ky)
+{
+    switch (B) {
+    case 8: return queue_get<8, 1, CL>(kx, ky);
+    case 16: return queue_get<16, 1, CL>(kx, ky);
+    case 32: return queue_get<16, 2, CL>(kx, ky);
+    case 64: return queue_get<16, 4, CL>(kx, ky);
+    default: return nullptr;
+    }
+}
+
+QueueFn queue_kernel_for(int B, int kx, int ky, int cl)
+{
+    return cl ? queue_kernel_for_cl<true>(B, kx, ky) : queue_kernel_for_cl<false>(B, kx, ky);
+}
+
+}  // namespace
+
+bool queue_supported(int B, int kx, int ky) { return queue_kernel_for(B, kx, ky, 0) != nullptr; }
 
 bool plan_tiles(int B, int R, size_t lds_cap, TileCfg* cfg)
 {
     const int n = 2 * R + 1;
-    if (cfg->nb < 1 || cfg->nb * kWavesPerBlock * 64 > kTiledMaxThreads) return false;
+    if (cfg->wpb == 0) cfg->wpb = kWavesPerBlock;
+    if (cfg->nb < 1 || (cfg->wpb != 2 && cfg->wpb != 4 && cfg->wpb != 8) ||
+        cfg->nb * cfg->wpb * 64 > kTiledMaxThreads)
+        return false;
     const int pitch = tiled_pitch(B, n, cfg->kx, cfg->nb);
     if (pitch > kMaxPitch) return false;
+    if (cfg->cl != 0 && cfg->cl != 1) return false;
+    const size_t cb = cur_bytes(B, cfg->nb, cfg->cl);
     int band = (n + cfg->ky - 1) / cfg->ky;
-    while (band > 1 && tiled_bytes(B, n, cfg->ky, band, pitch) > lds_cap) --band;
-    const size_t bytes = tiled_bytes(B, n, cfg->ky, band, pitch);
+    while (band > 1 && tiled_bytes(B, n, cfg->ky, band, pitch) + cb > lds_cap) --band;
+    const size_t bytes = tiled_bytes(B, n, cfg->ky, band, pitch) + cb;
     if (bytes > lds_cap) return false;
     cfg->band_ty = band;
     cfg->lds_pitch = pitch;
@@ -910,6 +1168,7 @@ TileCfg default_tiles(int B, int R)
 {
     TileCfg c{};
     c.kx = 4;
+    c.rs = 1;
     const int n = 2 * R + 1;
     // Two blocks per workgroup share one window when the radius keeps their
     // window starts 16-byte aligned (R % 4 == 0), within 80 KB (two workgroups
@@ -1006,7 +1265,7 @@ bool step_supported(int B, int R, int step)
     return step_plan(B, R, step, &p, &nyb, &by);
 }
 
-hipError_t launch_sad_search(const SearchArgs& a, const TileCfg& cfg_in, int n_wg, hipStream_t stream)
+hipError_t launch_sad_search(const SearchArgs& a, const TileCfg& cfg_in, int n_wg, hipStream_t stream, int parts)
 {
     const bool batch = a.jobs != nullptr;
     const int64_t njobs = batch ? a.n_jobs : 1;
@@ -1052,13 +1311,17 @@ hipError_t launch_sad_search(const SearchArgs& a, const TileCfg& cfg_in, int n_w
             !plan_tiles(a.block, a.R, kLdsMax, &cfg))
             return hipErrorInvalidValue;
     }
-    KernelFn k = batch ? kernel_for<true>(a.block, cfg.kx, cfg.ky) : kernel_for<false>(a.block, cfg.kx, cfg.ky);
-    if (!k || cfg.nb < 1 || cfg.nb * kWavesPerBlock * 64 > kTiledMaxThreads || (cfg.lds_pitch & 3))
+    KernelFn k = batch ? kernel_for<true>(a.block, cfg.kx, cfg.ky, cfg.cl)
+                       : kernel_for<false>(a.block, cfg.kx, cfg.ky, cfg.cl);
+    const int wpb = cfg.wpb ? cfg.wpb : kWavesPerBlock;
+    if (!k || cfg.nb < 1 || (wpb != 2 && wpb != 4 && wpb != 8) || cfg.nb * wpb * 64 > kTiledMaxThreads ||
+        (cfg.lds_pitch & 3))
         return hipErrorInvalidValue;
     const int n = 2 * a.R + 1;
     // the shape must cover the widest candidate window of this radius
+    const size_t wbytes = tiled_bytes(a.block, n, cfg.ky, cfg.band_ty, cfg.lds_pitch);
     if (cfg.band_ty < 1 || cfg.lds_pitch > kMaxPitch || cfg.lds_pitch < tiled_pitch(a.block, n, cfg.kx, cfg.nb) ||
-        tiled_bytes(a.block, n, cfg.ky, cfg.band_ty, cfg.lds_pitch) > cfg.lds_bytes || cfg.lds_bytes > kLdsMax)
+        wbytes + cur_bytes(a.block, cfg.nb, cfg.cl) > cfg.lds_bytes || cfg.lds_bytes > kLdsMax)
         return hipErrorInvalidValue;
     const int full_cols = a.Wp / a.block;           // block columns of full width
     const bool has_partial = full_cols < a.bw;
@@ -1086,31 +1349,81 @@ hipError_t launch_sad_search(const SearchArgs& a, const TileCfg& cfg_in, int n_w
     b.band_ty = cfg.band_ty;
     b.lds_pitch = cfg.lds_pitch;
     b.nb = cfg.nb;
+    b.wpb = wpb;
+    b.rs = cfg.rs;
+    b.cur_lds = (int32_t)(wbytes / 4);              // current blocks after the largest band's window
     SearchArgs c = a;
     c.band_ty = gband;
     c.lds_pitch = gpitch;
     c.nb = 1;
     if (a.list) {
         if (n_wg <= 0) return hipSuccess;
-        hipLaunchKernelGGL(k, dim3(n_wg), dim3(kWavesPerBlock * 64), cfg.lds_bytes, stream, b);
+        hipLaunchKernelGGL(k, dim3(n_wg), dim3(wpb * 64), cfg.lds_bytes, stream, b);
         if (has_partial) hipLaunchKernelGGL(gk, dim3(n_wg), dim3(256), gbytes, stream, c);
         return hipGetLastError();
     }
-    if (full_cols > 0) {
+    if (full_cols > 0 && (parts & 1)) {
         b.col0 = 0;
         b.ncols = full_cols;
         const int64_t groups = (full_cols + cfg.nb - 1) / cfg.nb;
         const int64_t grid = njobs * a.bh * groups;
         if (grid > 0x7fffffff) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(cfg.nb * kWavesPerBlock * 64), cfg.lds_bytes, stream, b);
+        hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(cfg.nb * wpb * 64), cfg.lds_bytes, stream, b);
     }
-    if (has_partial) {
+    if (has_partial && (parts & 2)) {
         c.col0 = full_cols;
         c.ncols = 1;
         const int64_t grid = njobs * a.bh;
         if (grid > 0x7fffffff) return hipErrorInvalidValue;
         hipLaunchKernelGGL(gk, dim3((unsigned)grid), dim3(256), gbytes, stream, c);
     }
+    return hipGetLastError();
+}
+
+bool plan_queue_job(int B, const TileCfg& tile, size_t lds_cap, QueueJob* j, size_t* lds_bytes)
+{
+    const int n = 2 * j->R + 1;
+    const int main_tasks = ((n / tile.kx) * (n / tile.ky) + 63) / 64;
+    // (blocks per item, waves per block), eight waves per workgroup: two blocks
+    // of four waves when a block's main tiles give each of its four waves a
+    // task, four blocks of two waves for small windows, one block of eight
+    // waves when blocks cannot share a window (radius % 4 != 0)
+    static const int pref[3][2][2] = {{{1, 8}, {0, 0}}, {{2, 4}, {1, 8}}, {{4, 2}, {2, 4}}};
+    const int (*opts)[2] = j->R % 4 ? pref[0] : (main_tasks >= 4 ? pref[1] : pref[2]);
+    for (int k = 0; k < 2 && opts[k][0] > 0; ++k) {
+        TileCfg c = tile;
+        c.nb = opts[k][0];
+        c.wpb = opts[k][1];
+        if (!plan_tiles(B, j->R, lds_cap, &c)) continue;
+        j->nb = c.nb;
+        j->wpb = c.wpb;
+        j->rs = c.rs;
+        j->band_ty = c.band_ty;
+        j->lds_pitch = c.lds_pitch;
+        j->cur_lds = (int32_t)((c.lds_bytes - cur_bytes(B, c.nb, c.cl)) / 4);
+        j->cols = j->Wp / B;
+        j->groups = (j->cols + c.nb - 1) / c.nb;
+        *lds_bytes = c.lds_bytes;
+        return true;
+    }
+    return false;
+}
+
+hipError_t launch_sad_queue(const QueueArgs& q, int B, const TileCfg& tile, size_t lds_bytes, hipStream_t stream)
+{
+    const QueueFn k = queue_kernel_for(B, tile.kx, tile.ky, tile.cl);
+    if (!k || lds_bytes > kLdsMax || q.n_jobs < 1 || !q.counter) return hipErrorInvalidValue;
+    if (q.n_items <= 0) return hipSuccess;
+    hipError_t e = set_lds(reinterpret_cast<const void*>(k), lds_bytes);
+    if (e != hipSuccess) return e;
+    int occ = 0, dev = 0, ncu = 0;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, kTiledMaxThreads, lds_bytes)) != hipSuccess ||
+        (e = hipGetDevice(&dev)) != hipSuccess ||
+        (e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+        return e;
+    const int64_t slots = (int64_t)(occ > 0 ? occ : 1) * (ncu > 0 ? ncu : 1);
+    const int grid = (int)(slots < q.n_items ? slots : q.n_items);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(kTiledMaxThreads), lds_bytes, stream, q);
     return hipGetLastError();
 }
 

@@ -361,18 +361,25 @@ def autotune(ctx: Context, ref, cur, block=16, radius=32, iters=3, stream=None) 
 
 def tuned_shape(ctx: Context, block, radius, height, width):
     """The launch shape used for (block, radius, height x width Bayer frames):
-    ((kx, ky, blocks per workgroup, LDS KB), tuned) with tuned True when it
-    was recorded by autotune or set_tuned_shape."""
-    shape = (ctypes.c_int32 * 4)()
+    ((kx, ky, blocks per workgroup, LDS KB, current block in LDS, waves per
+    block), tuned) with tuned True when it was recorded by autotune or
+    set_tuned_shape."""
+    shape = (ctypes.c_int32 * 6)()
     tuned = ctypes.c_int32()
     _check(_me_tuned_shape(ctx.handle, block, radius, height, width, ctypes.addressof(shape), ctypes.addressof(tuned)))
     return tuple(shape), bool(tuned.value)
 
 
 def set_tuned_shape(ctx: Context, block, radius, height, width, shape):
-    """Record a launch shape (kx, ky, blocks per workgroup, LDS budget in KB)
-    for (block, radius, frame size), e.g. one reported by tuned_shape."""
-    arr = (ctypes.c_int32 * 4)(*[int(v) for v in shape])
+    """Record a launch shape (kx, ky, blocks per workgroup, LDS budget in KB,
+    current block in LDS 0/1, waves per block; missing trailing entries mean
+    0 and 4) for (block, radius, frame size), e.g. one reported by
+    tuned_shape."""
+    vals = [int(v) for v in shape]
+    if not 4 <= len(vals) <= 6:
+        raise ValueError("shape has 4 to 6 entries")
+    vals += [0, 4][len(vals) - 4:]
+    arr = (ctypes.c_int32 * 6)(*vals)
     _check(_me_set_tuned_shape(ctx.handle, block, radius, height, width, ctypes.addressof(arr)))
 
 

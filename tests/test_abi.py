@@ -271,8 +271,8 @@ def test_estimate_warp_validation(me):
 
 def test_tuned_shape_validation(me):
     fake = ctypes.c_void_p(FAKE)
-    out = (ctypes.c_int32 * 4)()
-    ok_shape = (ctypes.c_int32 * 4)(4, 4, 2, 80)
+    out = (ctypes.c_int32 * 6)()
+    ok_shape = (ctypes.c_int32 * 6)(4, 4, 2, 80, 0, 4)
     get = lambda ctx, b, r, h, w, o: me._me_tuned_shape(ctx, b, r, h, w, o, None)
     assert get(None, 16, 32, 1080, 1920, ctypes.addressof(out)) == 1      # null context
     assert get(fake, 16, 32, 1080, 1920, None) == 1                       # null shape
@@ -281,12 +281,15 @@ def test_tuned_shape_validation(me):
     assert get(fake, 16, 32, 1081, 1920, ctypes.addressof(out)) == 1      # odd frame
     put = lambda sh, b=16, r=32: me._me_set_tuned_shape(fake, b, r, 1080, 1920, ctypes.addressof(sh))
     assert me._me_set_tuned_shape(None, 16, 32, 1080, 1920, ctypes.addressof(ok_shape)) == 1
-    assert put((ctypes.c_int32 * 4)(3, 4, 2, 80)) == 2                    # tile not compiled
-    assert put((ctypes.c_int32 * 4)(4, 4, 3, 80)) == 2                    # three blocks per workgroup
-    assert put((ctypes.c_int32 * 4)(4, 4, 2, 80), r=30) == 2              # two blocks need radius % 4 == 0
-    assert put((ctypes.c_int32 * 4)(4, 4, 1, 0)) == 2                     # no LDS budget
-    assert put((ctypes.c_int32 * 4)(4, 4, 1, 159)) == 2                   # beyond the LDS of a workgroup
-    assert put((ctypes.c_int32 * 4)(4, 4, 1, 1)) == 2                     # no band fits 1 KB
+    assert put((ctypes.c_int32 * 6)(3, 4, 2, 80, 0, 4)) == 2                    # tile not compiled
+    assert put((ctypes.c_int32 * 6)(4, 4, 3, 80, 0, 4)) == 2                    # three blocks per workgroup
+    assert put((ctypes.c_int32 * 6)(4, 4, 2, 80, 0, 4), r=30) == 2              # two blocks need radius % 4 == 0
+    assert put((ctypes.c_int32 * 6)(4, 4, 1, 0, 0, 4)) == 2                     # no LDS budget
+    assert put((ctypes.c_int32 * 6)(4, 4, 1, 159, 0, 4)) == 2                   # beyond the LDS of a workgroup
+    assert put((ctypes.c_int32 * 6)(4, 4, 1, 1, 0, 4)) == 2                     # no band fits 1 KB
+    assert put((ctypes.c_int32 * 6)(4, 4, 1, 80, 2, 4)) == 1                    # current-block source not 0/1
+    assert put((ctypes.c_int32 * 6)(4, 4, 1, 80, 0, 3)) == 1                    # waves per block not 2, 4 or 8
+    assert put((ctypes.c_int32 * 6)(4, 4, 2, 80, 0, 8)) == 2                    # 16 waves per workgroup
 
 
 def test_stats_validation(me):

@@ -1,6 +1,7 @@
-"""Batched submission (one persistent, graph-captured launch over many jobs of
-mixed sizes, block sizes and radii) and the launch-shape autotuner: results
-must be bit-identical to one me_estimate per job, and to the oracle."""
+"""Batched submission (one persistent, graph-captured work-queue launch per
+block size over many jobs of mixed sizes and radii, plus a per-shape launch
+for blocks cut by the right frame edge) and the launch-shape autotuner:
+results must be bit-identical to one me_estimate per job, and to the oracle."""
 import numpy as np
 import pytest
 
