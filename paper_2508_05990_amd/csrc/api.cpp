@@ -151,8 +151,7 @@ TileCfg tiles_for(me_ctx ctx, int B, int R, int Hp, int Wp)
 }
 
 me_status refine_run(const me_frame* ref, const me_frame* cur, const me_params& p, float m, const float* net_out,
-                     int16_t* mv, int32_t* sad, uint8_t* fallback, const RefineScratch& w, const TileCfg& full_tiles,
-                     hipStream_t st)
+                     int16_t* mv, int32_t* sad, uint8_t* fallback, const RefineScratch& w, hipStream_t st)
 {
     const int Hp = cur->height / 2, Wp = cur->width / 2;
     const int bh = (Hp + p.block - 1) / p.block, bw = (Wp + p.block - 1) / p.block;
@@ -179,7 +178,7 @@ me_status refine_run(const me_frame* ref, const me_frame* cur, const me_params& 
     SearchArgs f = make_args(ref, cur, p.block, p.radius, p.radius, nullptr, mv, sad);
     f.list = w.list;
     f.list_n = w.count;
-    e = launch_sad_search(f, full_tiles, nblk, st);
+    e = launch_sad_search(f, list_tiles(p.block, p.radius), nblk, st);
     if (e != hipSuccess) return hip_fail(e, "refine: fallback search");
     return ME_OK;
 }
@@ -194,7 +193,7 @@ me_status refine_impl(me_ctx ctx, const me_frame* ref, const me_frame* cur, cons
     me_status s = ensure_scratch(ctx, (size_t)bh * bw);
     if (s != ME_OK) return s;
     const RefineScratch w{ctx->pred, ctx->fb, ctx->list, ctx->count};
-    return refine_run(ref, cur, p, m, net_out, mv, sad, fallback, w, tiles_for(ctx, p.block, p.radius, Hp, Wp), st);
+    return refine_run(ref, cur, p, m, net_out, mv, sad, fallback, w, st);
 }
 
 me_status check_refine_params(const me_params& p)
@@ -577,8 +576,7 @@ me_status me_batch_submit(me_ctx ctx, const me_job* jobs, int32_t n, void* strea
 
     // plan (new shapes only):
     //  * full-width blocks: one persistent queue launch per block size over
-    //    all its jobs, jobs in decreasing order of work per item, tile shape of
-    //    the group's costliest job (tuned or default);
+    //    all its jobs, jobs in decreasing order of work per item;
     //  * blocks cut by the right frame edge: per-shape launches of the generic
     //    kernel over a (job, block row) grid, pointers from a shape-grouped table.
     std::vector<int32_t> slot((size_t)n);
@@ -607,37 +605,19 @@ me_status me_batch_submit(me_ctx ctx, const me_job* jobs, int32_t n, void* strea
         }
         for (int B : {8, 16, 32, 64}) {
             std::vector<int32_t> ks;
-            int32_t dom = -1;
-            double dom_cost = -1.0;
             for (int32_t k = 0; k < n; ++k) {
                 const me_job& j = jobs[k];
-                if (j.params.block != B || (j.cur.width / 2) / B == 0) continue;
-                ks.push_back(k);
-                const double nc = 2.0 * j.params.radius + 1.0;
-                const double cost = (double)(j.cur.height / 2) * (j.cur.width / 2) * nc * nc;
-                if (cost > dom_cost) {
-                    dom_cost = cost;
-                    dom = k;
-                }
+                if (j.params.block == B && (j.cur.width / 2) / B > 0) ks.push_back(k);
             }
             if (ks.empty()) continue;
-            // tile shape: the costliest job's tuned shape, else 4x2 tiles with
-            // scalar loads of the current block (the queue kernel's register
-            // count keeps four waves per SIMD with them)
-            const me_job& d = jobs[dom];
+            // tile shape of the queue kernel: 4x2 tiles, remainder rows as single
+            // candidates, current block through scalar loads (its register count
+            // keeps four waves per SIMD); per-pair tunings do not carry over, since
+            // the queue kernel's registers differ from the single-pair kernel's
             TileCfg tile{};
             tile.kx = 4;
             tile.ky = 2;
             tile.rs = 1;
-            {
-                std::lock_guard<std::mutex> g(ctx->mu);
-                auto it = ctx->tuned.find(std::make_tuple(B, d.params.radius, d.cur.height / 2, d.cur.width / 2));
-                if (it != ctx->tuned.end() && queue_supported(B, it->second.kx, it->second.ky)) {
-                    tile.kx = it->second.kx;
-                    tile.ky = it->second.ky;
-                    tile.cl = it->second.cl;
-                }
-            }
             QueueLaunch ql{};
             ql.block = B;
             ql.tile = tile;

@@ -134,8 +134,7 @@ struct RefineScratch {
 };
 // Refine + fallback given the median m and the scratch; no allocation.
 me_status refine_run(const me_frame* ref, const me_frame* cur, const me_params& p, float m, const float* net_out,
-                     int16_t* mv, int32_t* sad, uint8_t* fallback, const RefineScratch& w, const TileCfg& full_tiles,
-                     hipStream_t st);
+                     int16_t* mv, int32_t* sad, uint8_t* fallback, const RefineScratch& w, hipStream_t st);
 me_status check_refine_params(const me_params& p);
 // Refine + fallback on a network output already in device memory.
 me_status refine_impl(me_ctx ctx, const me_frame* ref, const me_frame* cur, const me_params& p, const float* net_out,

@@ -113,6 +113,10 @@ bool plan_tiles(int B, int R, size_t lds_cap, TileCfg* cfg);
 // Default launch shape for block size B and radius R.
 TileCfg default_tiles(int B, int R);
 
+// Launch shape of the full search over a device block list (one block per
+// workgroup).
+TileCfg list_tiles(int B, int R);
+
 // Whether the kernel table has an instance for (B, kx, ky).
 bool tiles_supported(int B, int kx, int ky);
 

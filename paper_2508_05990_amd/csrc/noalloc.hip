@@ -77,6 +77,5 @@ extern "C" me_status me_refine_noalloc(me_ctx ctx, const me_frame* ref, const me
     if (!base) return fail(ME_E_STATE, "me_refine_noalloc: scratch of device %d not resolved", ctx->device);
     const RefineScratch w{reinterpret_cast<int16_t*>(base + kOffPred), base + kOffFb,
                           reinterpret_cast<int32_t*>(base + kOffList), reinterpret_cast<int32_t*>(base + kOffCount)};
-    return refine_run(ref, cur, p, m, net_out, mv, sad, fallback, w, tiles_for(ctx, p.block, p.radius, Hp, Wp),
-                      reinterpret_cast<hipStream_t>(stream));
+    return refine_run(ref, cur, p, m, net_out, mv, sad, fallback, w, reinterpret_cast<hipStream_t>(stream));
 }

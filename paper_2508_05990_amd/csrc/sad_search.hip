@@ -727,12 +727,15 @@ __global__ __launch_bounds__(kTiledMaxThreads) void sad_search_kernel(SearchArgs
 // Persistent search over a queue of items from many frame pairs of one block
 // size (the paper's (Batch, h, w) grid with uneven jobs in one launch): each
 // workgroup repeatedly takes the next item -- a group of a job's horizontally
-// adjacent full-width blocks -- from a device counter and searches it with the
-// tiled code above, until the queue is empty.  Items are ordered by job
-// (costlier jobs first on the host side), so every workgroup stays busy until
-// the last items, whatever the mix of frame sizes and radii.  The workgroup
-// that draws the last ticket (n_items + gridDim.x - 1; every workgroup draws
-// exactly one past the end) sets the counter back to zero for the next launch.
+// adjacent full-width blocks -- and searches it with the tiled code above,
+// until the queue is empty: workgroup b starts with item b, then draws item
+// gridDim.x + ticket from a device counter after each item (so the counter is
+// not hit by every workgroup at once).  Items are ordered by job (costlier
+// jobs first on the host side), so every workgroup stays busy until the last
+// items, whatever the mix of frame sizes and radii.  Each workgroup that had an
+// item draws exactly one ticket past the end, so the draw that returns item
+// gridDim.x + n_items - 1 is the last one: that workgroup sets the counter back
+// to zero for the next launch.
 template <int CW, int NCH, int KX, int KY, bool CL>
 __global__ __launch_bounds__(kTiledMaxThreads) void sad_queue_kernel(QueueArgs q)
 {
@@ -740,12 +743,8 @@ __global__ __launch_bounds__(kTiledMaxThreads) void sad_queue_kernel(QueueArgs q
     __shared__ uint64_t red[kMaxWaves];
     __shared__ int s_item;
     constexpr int B = CW * NCH;
-    int item;
+    int item = blockIdx.x;                            // first item: the workgroup's own; then tickets
     for (;;) {
-        __syncthreads();                              // previous item's window, keys and ticket are free
-        if (threadIdx.x == 0) s_item = atomicAdd(q.counter, 1);
-        __syncthreads();
-        item = __builtin_amdgcn_readfirstlane(s_item);
         if (item >= q.n_items) break;
         int lo = 0, hi = q.n_jobs - 1;                // last job whose first item is <= item
         while (lo < hi) {
@@ -784,8 +783,12 @@ __global__ __launch_bounds__(kTiledMaxThreads) void sad_queue_kernel(QueueArgs q
         const int c0 = gj * j.nb;
         run_tiled<CW, NCH, KX, KY, CL>(a, bi * j.bw + c0, min(j.nb, j.cols - c0), reinterpret_cast<uint32_t*>(lds_dyn),
                                        red);
+        __syncthreads();                              // the item's window, keys and ticket slot are free
+        if (threadIdx.x == 0) s_item = (int)gridDim.x + atomicAdd(q.counter, 1);
+        __syncthreads();
+        item = __builtin_amdgcn_readfirstlane(s_item);
     }
-    if (threadIdx.x == 0 && item == q.n_items + (int)gridDim.x - 1) atomicExch(q.counter, 0);
+    if (threadIdx.x == 0 && item == (int)gridDim.x + q.n_items - 1) atomicExch(q.counter, 0);
 }
 
 // Blocks cut by the right frame edge: one candidate per lane, runtime width.
@@ -1162,6 +1165,24 @@ bool plan_tiles(int B, int R, size_t lds_cap, TileCfg* cfg)
     cfg->lds_pitch = pitch;
     cfg->lds_bytes = bytes;
     return true;
+}
+
+TileCfg list_tiles(int B, int R)
+{
+    // a listed block takes the whole workgroup: eight waves on 4x2 tiles when
+    // its main tiles give each of them a task (a short list then still keeps
+    // the chip's SIMDs busy), else four
+    TileCfg c{};
+    c.kx = 4;
+    c.ky = 2;
+    c.nb = 1;
+    c.rs = 1;
+    const int n = 2 * R + 1;
+    c.wpb = ((n / 4) * (n / 2) + 63) / 64 >= 8 ? 8 : 4;
+    if (plan_tiles(B, R, kLdsMid, &c) || plan_tiles(B, R, kLdsMax, &c)) return c;
+    c.wpb = 4;
+    if (plan_tiles(B, R, kLdsMid, &c) || plan_tiles(B, R, kLdsMax, &c)) return c;
+    return default_tiles(B, R);
 }
 
 TileCfg default_tiles(int B, int R)
