@@ -175,28 +175,51 @@ __device__ __forceinline__ void tile_sads(cptr_t curp, int64_t cur_pitch, int h,
             cptr_t nxt = ccol + rstep;                     // block row par + 2 (st + 1)
             // step st (u = st mod KY2): SADs against block row cu; block row par + 2 (st + 1)
             // into cx (the last step reloads row par, which is in the block)
-            auto one = [&](const int u, const int st, const uint32_t(&cu)[CW], uint32_t(&cx)[CW]) {
+            // SADs of candidate row j of the tile against block row cu (ring slot (u + j) mod KY)
+            auto row_sads = [&](const int u, const int j, const uint32_t(&cu)[CW]) {
+                uint32_t seg[SEGV * 4];
 #pragma unroll
-                for (int v = 0; v < SEGV; ++v) ring[(u + KY - 1) % KY][v] = col4[(2 * (st + KY - 1)) * pitch4 + v];
+                for (int v = 0; v < SEGV; ++v) {
+                    const uint4 t4 = ring[(u + j) % KY][v];
+                    seg[4 * v + 0] = t4.x;
+                    seg[4 * v + 1] = t4.y;
+                    seg[4 * v + 2] = t4.z;
+                    seg[4 * v + 3] = t4.w;
+                }
+#pragma unroll
+                for (int k = 0; k < CW; ++k)
+#pragma unroll
+                    for (int i = 0; i < KX; ++i) acc[j][i] = __builtin_amdgcn_sad_u16(cu[k], seg[k + i], acc[j][i]);
+            };
+            auto loads = [&](const int u, const int st, uint32_t(&cx)[CW]) {
                 const cptr_t src = st + 1 < h ? nxt : ccol;
 #pragma unroll
                 for (int k = 0; k < CW; ++k) cx[k] = src[k];
                 nxt += rstep;
 #pragma unroll
-                for (int j = 0; j < KY; ++j) {
-                    uint32_t seg[SEGV * 4];
+                for (int v = 0; v < SEGV; ++v) ring[(u + KY - 1) % KY][v] = col4[(2 * (st + KY - 1)) * pitch4 + v];
+            };
+            auto one = [&](const int u, const int st, const uint32_t(&cu)[CW], uint32_t(&cx)[CW]) {
+                if constexpr (KY >= 3) {
+                    // Scalar and LDS loads share one wait counter and scalar loads
+                    // return out of order, so any wait for an LDS read also waits
+                    // for every scalar load in flight.  Fixed order per step: the
+                    // first candidate row (its wait covers only the block row
+                    // requested a step earlier), then the next block row and the new
+                    // ring slot, then the rows held in registers, and only then the
+                    // row that needs the new slot, half a step after its request.
+                    row_sads(u, 0, cu);
+                    __builtin_amdgcn_sched_barrier(0);
+                    loads(u, st, cx);
+                    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                    for (int v = 0; v < SEGV; ++v) {
-                        const uint4 t4 = ring[(u + j) % KY][v];
-                        seg[4 * v + 0] = t4.x;
-                        seg[4 * v + 1] = t4.y;
-                        seg[4 * v + 2] = t4.z;
-                        seg[4 * v + 3] = t4.w;
-                    }
+                    for (int j = 1; j < KY - 1; ++j) row_sads(u, j, cu);
+                    __builtin_amdgcn_sched_barrier(0);
+                    row_sads(u, KY - 1, cu);
+                } else {
+                    loads(u, st, cx);
 #pragma unroll
-                    for (int k = 0; k < CW; ++k)
-#pragma unroll
-                        for (int i = 0; i < KX; ++i) acc[j][i] = __builtin_amdgcn_sad_u16(cu[k], seg[k + i], acc[j][i]);
+                    for (int j = 0; j < KY; ++j) row_sads(u, j, cu);
                 }
             };
 #pragma unroll 1
