@@ -90,9 +90,10 @@ def proposal_leg(me, ctx, frames, mvs_exh, z, outs, B, R, H, W, args):
     """Learned-proposal mode on the same sequence (same GPU, same warp):
     frames/s, MV-error rate against full search (Euclidean error > 1 packed
     pixel) and fallback rate, for the trained network with the confidence and
-    SAD fallbacks (confidence 0.5, SAD 1.5 x median), for the same network
-    with the SAD fallback only, and for the method without the network (zero
-    proposals, same refine and fallback)."""
+    SAD fallbacks (the logit threshold stored with the weights, chosen on
+    validation sequences; SAD 1.5 x median), for the same network with the
+    SAD fallback only, and for the method without the network (zero
+    proposals, same refine and SAD fallback)."""
     import numpy as np
     import torch
 
@@ -101,7 +102,7 @@ def proposal_leg(me, ctx, frames, mvs_exh, z, outs, B, R, H, W, args):
     path = args.weights or train.DEFAULT_WEIGHTS
     if not os.path.exists(path):
         return {"skipped": "no weights at %s" % path}
-    params, median = train.load_weights(path)
+    params, median, thr = train.load_weights(path)
     me.cnn_set_params(ctx, params, median)
     npairs = len(frames) - 1
     bh, bw = mvs_exh[0].shape[:2]
@@ -121,7 +122,7 @@ def proposal_leg(me, ctx, frames, mvs_exh, z, outs, B, R, H, W, args):
                 if use_net:
                     me.estimate(frames[t], frames[t + 1], mv=mv[t], sad=sad[t], fallback=fb[t], params=p, ctx=ctx)
                 else:
-                    me.refine(frames[t], frames[t + 1], zero, ctx, B, R, rr, conf, 1.5, median, mv=mv[t],
+                    me.refine(frames[t], frames[t + 1], zero, ctx, B, R, rr, -1e30, 1.5, median, mv=mv[t],
                               sad=sad[t], fallback=fb[t])
                 if ev is not None:
                     ev[t][1].record()
@@ -148,8 +149,9 @@ def proposal_leg(me, ctx, frames, mvs_exh, z, outs, B, R, H, W, args):
         return {"value": round(npairs * args.steps / wall, 2), "unit": "frames/s", "me_ms_per_pair": round(me_ms, 4),
                 "mv_err_rate": err / nb, "fallback_rate": round(fall / nb, 5)}
 
-    res = run_mode(0.0, True)
-    res.update({"refine_radius": rr, "weights": os.path.relpath(path, ROOT), "ms_per_pair": round(1e3 / res["value"], 4)})
+    res = run_mode(thr, True)
+    res.update({"refine_radius": rr, "logit_threshold": thr, "weights": os.path.relpath(path, ROOT),
+                "ms_per_pair": round(1e3 / res["value"], 4)})
     res["sad_fallback_only"] = run_mode(-1e30, True)
     res["zero_proposal"] = run_mode(0.0, False)
     return res
@@ -489,7 +491,7 @@ def batched_leg(me, ctx, args):
 def uhd_leg(me, ctx, args):
     """3840x2160 sequence with 32 moving rectangles and a background pan, B=16
     R=64, each pair followed by a bfloat16 warp of [256, 270, 480]: full
-    search, the learned-proposal mode (trained network, confidence 0.5 and
+    search, the learned-proposal mode (trained network, stored logit threshold and
     SAD 1.5 x median fallbacks) and the same refine + fallback with zero
     proposals.  Per mode: frames/s, ME time per pair, MV-error rate against
     full search (Euclidean error > 1 packed pixel; full search is the oracle's
@@ -514,10 +516,10 @@ def uhd_leg(me, ctx, args):
     zero = torch.zeros((3, bh, bw), dtype=torch.float32, device="cuda")
     steps = max(2, args.steps // 4)
     path = args.weights or train.DEFAULT_WEIGHTS
-    params, median = train.load_weights(path)
+    params, median, thr = train.load_weights(path)
     me.cnn_set_params(ctx, params, median)
     p_exh = me.make_params(B, R)
-    p_net = me.make_params(B, R, me.ME_MODE_PROPOSAL, rr, 0.0, 1.5, 0.0)
+    p_net = me.make_params(B, R, me.ME_MODE_PROPOSAL, rr, thr, 1.5, 0.0)
 
     def run(mode):
         ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps * npairs)]
@@ -535,7 +537,8 @@ def uhd_leg(me, ctx, args):
                     me.estimate(fr[t], fr[t + 1], mv=mv, sad=sad, fallback=fb, params=p_net, ctx=ctx)
                     out = mv
                 else:
-                    me.refine(fr[t], fr[t + 1], zero, ctx, B, R, rr, 0.0, 1.5, median, mv=mv, sad=sad, fallback=fb)
+                    me.refine(fr[t], fr[t + 1], zero, ctx, B, R, rr, -1e30, 1.5, median, mv=mv, sad=sad,
+                              fallback=fb)
                     out = mv
                 if e:
                     e[1].record()

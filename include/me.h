@@ -259,15 +259,16 @@ me_status me_refine_noalloc(me_ctx ctx, const me_frame* ref, const me_frame* cur
 /*
  * Proposal network (learned-proposal mode; this library's addition, see
  * me_refine).  Input: for a frame pair of H x W Bayer samples (H, W divisible
- * by 4), the 2x2 means of the four packed planes of the reference (channels
- * 0-3) and current frame (4-7), normalised to (v - 2048) / 1024, bfloat16,
- * channels last [H/4][W/4][8].  Four 3x3 convolutions, zero padding 1,
- * strides 2, 2, 2, 1, channels 8 -> 32 -> 32 -> 32 -> 3, ReLU after the first
+ * by 8), the 4x4 means of each of the four packed planes of the reference
+ * (channels 0-3) and current frame (4-7) -- the packed pair at a quarter of its
+ * resolution per axis -- normalised to (v - 2048) / 1024, bfloat16, channels
+ * last [H/8][W/8][8].  Four 3x3 convolutions, zero padding 1,
+ * strides 2, 2, 1, 1, channels 8 -> 32 -> 32 -> 32 -> 3, ReLU after the first
  * three, bfloat16 weights and activations with float32 accumulation (MFMA);
  * output float32 [3][bh][bw] per pair for 16x16 blocks: mvx, mvy (units of 8
  * packed pixels) and a confidence logit.  Training loss: mean over blocks of
  * the reverse Huber (BerHu, paper Sec. 3.3) of each vector component against
- * full-search vector / 8 (threshold 1/8), plus the binary cross-entropy of
+ * full-search vector / 8 (threshold 1, i.e. 8 packed pixels), plus the binary cross-entropy of
  * the logit against "the full-search vector lies within refine_radius of the
  * decoded proposal"; AdamW (beta 0.9/0.999, eps 1e-8, weight decay 0.01) as
  * in the paper's training details (Sec. 4.1).
@@ -284,7 +285,7 @@ me_status me_refine_noalloc(me_ctx ctx, const me_frame* ref, const me_frame* cur
 me_status me_cnn_set_params(me_ctx ctx, const float* params, int32_t count, float median_per_sample);
 /* Copy the master parameters (and median, if not NULL) to host memory.  Synchronous. */
 me_status me_cnn_get_params(me_ctx ctx, float* params, int32_t count, float* median_per_sample);
-/* Network input of one frame pair into x (device bfloat16 [H/4][W/4][8]). */
+/* Network input of one frame pair into x (device bfloat16 [H/8][W/8][8]). */
 me_status me_cnn_pool(me_ctx ctx, const me_frame* ref, const me_frame* cur, uint16_t* x, void* stream);
 /* Forward of n pooled inputs x ([n][Hq][Wq][8]) into out (device float32 [n][3][bh][bw]). */
 me_status me_cnn_forward(me_ctx ctx, const uint16_t* x, int32_t n, int32_t Hq, int32_t Wq, float* out, void* stream);

@@ -13,12 +13,14 @@ What the paper fixes and this reuses:
   1e-6, batch 16 (Sec. 4.1, training details).
 
 The network itself (a project choice, stated here because the paper is
-silent): input = 2x2 mean of the four packed planes of reference and
-current frame (8 channels, a quarter of the Bayer resolution per axis),
-normalised to (v - 2048) / 1024; four 3x3 convolutions with zero padding 1,
-strides 2, 2, 2, 1, channels 8 -> 32 -> 32 -> 32 -> 3, ReLU after the first
-three; output per block of 16x16 packed pixels: (mvx, mvy) in units of 8
-packed pixels and a confidence logit.  Weights and activations are bfloat16
+silent): input = 4x4 mean of each of the four packed planes of reference and
+current frame (8 channels, the packed frame pair at a quarter of its
+resolution per axis), normalised to (v - 2048) / 1024; four 3x3 convolutions
+with zero padding 1, strides 2, 2, 1, 1, channels 8 -> 32 -> 32 -> 32 -> 3,
+ReLU after the first three; output per block of 16x16 packed pixels:
+(mvx, mvy) in units of 8 packed pixels and a confidence logit.  The reverse
+Huber threshold is one output unit (8 packed pixels): absolute error below
+it, squared beyond.  Weights and activations are bfloat16
 (round to nearest even) and biases are used as given (the float32 master
 values); sums are exact here; the gradient of a rounding step is taken as 1.
 """
@@ -26,9 +28,9 @@ from __future__ import annotations
 
 import numpy as np
 
-LAYERS = ((8, 32, 2), (32, 32, 2), (32, 32, 2), (32, 3, 1))   # (in channels, out channels, stride)
+LAYERS = ((8, 32, 2), (32, 32, 2), (32, 32, 1), (32, 3, 1))   # (in channels, out channels, stride)
 NPARAMS = sum(co * ci * 9 + co for ci, co, _ in LAYERS)          # 21699
-BERHU_C = 1.0 / 8.0
+BERHU_C = 1.0
 
 
 def bf16_round(x):
@@ -75,12 +77,12 @@ def init_params(seed):
 
 
 def pool_input(ref_planes, cur_planes, rnd=bf16_round):
-    """[8, Hp/2, Wp/2]: 2x2 means of the packed planes of ref (channels 0-3) and
+    """[8, Hp/4, Wp/4]: 4x4 means of the packed planes of ref (channels 0-3) and
     cur (4-7), normalised to (v - 2048) / 1024, then rounded."""
     out = []
     for P in (ref_planes, cur_planes):
         P = np.asarray(P, dtype=np.float64)
-        q = (P[:, 0::2, 0::2] + P[:, 0::2, 1::2] + P[:, 1::2, 0::2] + P[:, 1::2, 1::2]) / 4.0
+        q = sum(P[:, i::4, j::4] for i in range(4) for j in range(4)) / 16.0
         out.append((q - 2048.0) / 1024.0)
     return rnd(np.concatenate(out, axis=0))
 

@@ -282,8 +282,8 @@ me_status me_estimate(me_ctx ctx, const me_frame* ref, const me_frame* cur, cons
         if (!ctx || !ctx->cnn.loaded) return fail(ME_E_STATE, "me_estimate: proposal mode needs loaded weights");
         s = check_refine_params(p);
         if (s != ME_OK) return s;
-        if (p.block != 16 || (cur->height % 4) || (cur->width % 4))
-            return fail(ME_E_UNSUPPORTED, "me_estimate: proposal mode needs B=16 and frame sides divisible by 4");
+        if (p.block != 16 || (cur->height % 8) || (cur->width % 8))
+            return fail(ME_E_UNSUPPORTED, "me_estimate: proposal mode needs B=16 and frame sides divisible by 8");
         s = cnn_propose(ctx, ref, cur, st);
         if (s != ME_OK) return s;
         return refine_impl(ctx, ref, cur, p, ctx->cnn.out, mv, sad, fallback, st);

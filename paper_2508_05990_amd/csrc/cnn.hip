@@ -1,12 +1,14 @@
 // Proposal network of the learned-proposal mode on gfx950: forward, loss,
 // backward and AdamW, all as HIP kernels (bfloat16 MFMA, float32 accumulate).
 //
-// Network: input = 2x2 mean of the four packed planes of reference and
-// current frame (8 channels), normalised to (v - 2048) / 1024; four 3x3
-// convolutions, zero padding 1, strides 2, 2, 2, 1, channels
+// Network: input = 4x4 mean of each of the four packed planes of reference
+// and current frame (8 channels: the packed pair at a quarter of its
+// resolution per axis), normalised to (v - 2048) / 1024; four 3x3
+// convolutions, zero padding 1, strides 2, 2, 1, 1, channels
 // 8 -> 32 -> 32 -> 32 -> 3, ReLU after the first three; output per 16x16
 // block: (mvx, mvy) in units of 8 packed pixels and a confidence logit.
-// Loss: reverse Huber (BerHu, paper Sec. 3.3) on the vector, binary
+// Loss: reverse Huber (BerHu, paper Sec. 3.3; threshold one output unit,
+// 8 packed pixels) on the vector, binary
 // cross-entropy of the logit against "the full-search vector lies in the
 // refine window of the decoded proposal"; optimiser AdamW with a cosine
 // schedule (paper Sec. 4.1, training details).
@@ -32,8 +34,10 @@ namespace {
 
 // out[y][x][c]: c < 4 from ref, c >= 4 from cur; plane c of a mosaic is
 // sample (2py + (c>>1), 2px + (c&1)), and output pixel (y, x) averages packed
-// pixels (2y..2y+1, 2x..2x+1), i.e. mosaic rows 4y + (c>>1) + {0,2} and
-// columns 4x + (c&1) + {0,2}.
+// pixels (4y..4y+3, 4x..4x+3), i.e. the 16 samples of colour c in the 8 x 8
+// mosaic cell at rows 8y.., columns 8x..: rows 8y + (c>>1) + {0,2,4,6},
+// columns 8x + (c&1) + {0,2,4,6}.  Sums are exact integers; the mean is
+// scaled by a power of two, so the only rounding is the final bfloat16 one.
 __global__ void pool_kernel(const uint16_t* __restrict__ ref, int64_t ref_pitch, const uint16_t* __restrict__ cur,
                             int64_t cur_pitch, int Hq, int Wq, uint16_t* __restrict__ out)
 {
@@ -45,28 +49,31 @@ __global__ void pool_kernel(const uint16_t* __restrict__ ref, int64_t ref_pitch,
     for (int f = 0; f < 2; ++f) {
         const uint16_t* m = f ? cur : ref;
         const int64_t pitch = f ? cur_pitch : ref_pitch;
-        // the 4 x 4 mosaic samples of the cell: one 8-byte load per row when rows are 8-byte aligned
-        uint32_t q[4][4];
-        if ((pitch & 3) == 0 && (reinterpret_cast<uintptr_t>(m) & 7) == 0) {
+        // per mosaic row of the cell, the sums of its even and odd columns
+        uint32_t se[8], so[8];
+        if ((pitch & 7) == 0 && (reinterpret_cast<uintptr_t>(m) & 15) == 0) {
+            uint4 u[8];                                   // one 16-byte load per row, all issued first
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const uint2 u = *reinterpret_cast<const uint2*>(m + (4LL * y + r) * pitch + 4LL * x);
-                q[r][0] = u.x & 0xffffu;
-                q[r][1] = u.x >> 16;
-                q[r][2] = u.y & 0xffffu;
-                q[r][3] = u.y >> 16;
+            for (int r = 0; r < 8; ++r) u[r] = *reinterpret_cast<const uint4*>(m + (8LL * y + r) * pitch + 8LL * x);
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                se[r] = (u[r].x & 0xffffu) + (u[r].y & 0xffffu) + (u[r].z & 0xffffu) + (u[r].w & 0xffffu);
+                so[r] = (u[r].x >> 16) + (u[r].y >> 16) + (u[r].z >> 16) + (u[r].w >> 16);
             }
         } else {
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int k = 0; k < 4; ++k) q[r][k] = m[(4LL * y + r) * pitch + 4LL * x + k];
+            for (int r = 0; r < 8; ++r) {
+                const uint16_t* row = m + (8LL * y + r) * pitch + 8LL * x;
+                se[r] = (uint32_t)row[0] + row[2] + row[4] + row[6];
+                so[r] = (uint32_t)row[1] + row[3] + row[5] + row[7];
+            }
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            const int r0 = c >> 1, c0 = c & 1;
-            const uint32_t s = q[r0][c0] + q[r0][c0 + 2] + q[r0 + 2][c0] + q[r0 + 2][c0 + 2];
-            v[4 * f + c] = ((float)s * 0.25f - 2048.0f) * (1.0f / 1024.0f);
+            const int r0 = c >> 1;
+            const uint32_t* cs = (c & 1) ? so : se;
+            const uint32_t s = cs[r0] + cs[r0 + 2] + cs[r0 + 4] + cs[r0 + 6];
+            v[4 * f + c] = ((float)s * 0.0625f - 2048.0f) * (1.0f / 1024.0f);
         }
     }
     uint4 w;
@@ -84,7 +91,7 @@ struct LayerDesc {
 };
 
 __constant__ LayerDesc kLayers[4] = {
-    {8, 32, 2, 0, 2304}, {32, 32, 2, 2336, 11552}, {32, 32, 2, 11584, 20800}, {32, 3, 1, 20832, 21696}};
+    {8, 32, 2, 0, 2304}, {32, 32, 2, 2336, 11552}, {32, 32, 1, 11584, 20800}, {32, 3, 1, 20832, 21696}};
 
 // Forward A operand of layer l: [mt][ks][lane][4], m = out channel, k = tap*cin + c.
 // Input-gradient A operand: [ct][ks][lane][4], m = in channel, k = tap*coutp + o.
@@ -285,7 +292,7 @@ __global__ void loss_kernel(const float* __restrict__ out, const int16_t* __rest
     const float px = fminf(fmaxf(rintf(8.f * ox), -r), r), py = fminf(fmaxf(rintf(8.f * oy), -r), r);
     const float dmax = fmaxf(fabsf(px - (float)mx), fabsf(py - (float)my));
     const float y = dmax <= (float)rr ? 1.f : 0.f;
-    const float c = 0.125f;
+    const float c = 1.0f;                          // one output unit = 8 packed pixels
     const float ex = ox - (float)mx * 0.125f, ey = oy - (float)my * 0.125f;
     const float bce = fmaxf(lg, 0.f) - lg * y + log1pf(expf(-fabsf(lg)));
     const float w = wt ? wt[e] : 1.f;              // weight of the vector term
@@ -540,7 +547,7 @@ hipError_t launch_conv_fwd(int l, const uint16_t* in, const uint16_t* wp, const 
         switch (l) {
         case 0: hipLaunchKernelGGL((conv_fwd_split_kernel<8, 32, 2, false>), sg, blk, 0, st, in, wp, bias, out, n, H, W, Ho, Wo); break;
         case 1: hipLaunchKernelGGL((conv_fwd_split_kernel<32, 32, 2, false>), sg, blk, 0, st, in, wp, bias, out, n, H, W, Ho, Wo); break;
-        case 2: hipLaunchKernelGGL((conv_fwd_split_kernel<32, 32, 2, false>), sg, blk, 0, st, in, wp, bias, out, n, H, W, Ho, Wo); break;
+        case 2: hipLaunchKernelGGL((conv_fwd_split_kernel<32, 32, 1, false>), sg, blk, 0, st, in, wp, bias, out, n, H, W, Ho, Wo); break;
         case 3: hipLaunchKernelGGL((conv_fwd_split_kernel<32, 3, 1, true>), sg, blk, 0, st, in, wp, bias, out, n, H, W, Ho, Wo); break;
         default: return hipErrorInvalidValue;
         }
@@ -549,7 +556,7 @@ hipError_t launch_conv_fwd(int l, const uint16_t* in, const uint16_t* wp, const 
     switch (l) {
     case 0: hipLaunchKernelGGL((conv_fwd_kernel<8, 32, 2, false>), grid, blk, 0, st, in, wp, bias, out, n, H, W, Ho, Wo); break;
     case 1: hipLaunchKernelGGL((conv_fwd_kernel<32, 32, 2, false>), grid, blk, 0, st, in, wp, bias, out, n, H, W, Ho, Wo); break;
-    case 2: hipLaunchKernelGGL((conv_fwd_kernel<32, 32, 2, false>), grid, blk, 0, st, in, wp, bias, out, n, H, W, Ho, Wo); break;
+    case 2: hipLaunchKernelGGL((conv_fwd_kernel<32, 32, 1, false>), grid, blk, 0, st, in, wp, bias, out, n, H, W, Ho, Wo); break;
     case 3: hipLaunchKernelGGL((conv_fwd_kernel<32, 3, 1, true>), grid, blk, 0, st, in, wp, bias, out, n, H, W, Ho, Wo); break;
     default: return hipErrorInvalidValue;
     }
@@ -574,8 +581,8 @@ hipError_t launch_conv_dgrad(int l, const uint16_t* dz, const uint16_t* wb, cons
     const int P = n * H * W;
     dim3 grid(div_up(P, 64)), blk(256);
     switch (l) {
-    case 1:
-    case 2: hipLaunchKernelGGL((conv_dgrad_kernel<32, 32, 2>), grid, blk, 0, st, dz, wb, aprev, dprev, n, H, W, Ho, Wo); break;
+    case 1: hipLaunchKernelGGL((conv_dgrad_kernel<32, 32, 2>), grid, blk, 0, st, dz, wb, aprev, dprev, n, H, W, Ho, Wo); break;
+    case 2: hipLaunchKernelGGL((conv_dgrad_kernel<32, 32, 1>), grid, blk, 0, st, dz, wb, aprev, dprev, n, H, W, Ho, Wo); break;
     case 3: hipLaunchKernelGGL((conv_dgrad_kernel<32, 4, 1>), grid, blk, 0, st, dz, wb, aprev, dprev, n, H, W, Ho, Wo); break;
     default: return hipErrorInvalidValue;
     }
@@ -601,8 +608,8 @@ hipError_t launch_conv_wgrad(int l, const uint16_t* x, const uint16_t* dz, float
     dim3 grid(nwg), blk(256);
     switch (l) {
     case 0: hipLaunchKernelGGL((conv_wgrad_kernel<8, 32, 32, 2>), grid, blk, 0, st, x, dz, partial, n, H, W, Ho, Wo); break;
-    case 1:
-    case 2: hipLaunchKernelGGL((conv_wgrad_kernel<32, 32, 32, 2>), grid, blk, 0, st, x, dz, partial, n, H, W, Ho, Wo); break;
+    case 1: hipLaunchKernelGGL((conv_wgrad_kernel<32, 32, 32, 2>), grid, blk, 0, st, x, dz, partial, n, H, W, Ho, Wo); break;
+    case 2: hipLaunchKernelGGL((conv_wgrad_kernel<32, 32, 32, 1>), grid, blk, 0, st, x, dz, partial, n, H, W, Ho, Wo); break;
     case 3: hipLaunchKernelGGL((conv_wgrad_kernel<32, 3, 4, 1>), grid, blk, 0, st, x, dz, partial, n, H, W, Ho, Wo); break;
     default: return hipErrorInvalidValue;
     }

@@ -15,7 +15,9 @@ namespace {
 constexpr int kOffW[4] = {0, 2336, 11584, 20832};
 constexpr int kOffB[4] = {2304, 11552, 20800, 21696};
 
-int half_up(int n) { return (n + 1) / 2; }
+constexpr int kStride[4] = {2, 2, 1, 1};
+
+int out_dim(int l, int n) { return (n + kStride[l] - 1) / kStride[l]; }
 
 struct Dims {
     int h[5], w[5];   // h[0] = Hq (input), h[l+1] = output of layer l
@@ -26,12 +28,10 @@ Dims dims_of(int Hq, int Wq)
     Dims d;
     d.h[0] = Hq;
     d.w[0] = Wq;
-    for (int l = 0; l < 3; ++l) {
-        d.h[l + 1] = half_up(d.h[l]);
-        d.w[l + 1] = half_up(d.w[l]);
+    for (int l = 0; l < 4; ++l) {
+        d.h[l + 1] = out_dim(l, d.h[l]);
+        d.w[l + 1] = out_dim(l, d.w[l]);
     }
-    d.h[4] = d.h[3];
-    d.w[4] = d.w[3];
     return d;
 }
 
@@ -142,7 +142,7 @@ void CnnState::release()
 
 me_status cnn_propose(me_ctx ctx, const me_frame* ref, const me_frame* cur, hipStream_t st)
 {
-    const int Hq = cur->height / 4, Wq = cur->width / 4;
+    const int Hq = cur->height / 8, Wq = cur->width / 8;
     me_status s = ensure_acts(ctx, 1, Hq, Wq);
     if (s != ME_OK) return s;
     CnnState& c = ctx->cnn;
@@ -199,9 +199,9 @@ me_status me_cnn_pool(me_ctx ctx, const me_frame* ref, const me_frame* cur, uint
     if (s != ME_OK) return s;
     if (!x) return fail(ME_E_INVAL, "me_cnn_pool: null output");
     if (reinterpret_cast<uintptr_t>(x) & 15u) return fail(ME_E_INVAL, "me_cnn_pool: output must be 16-byte aligned");
-    if ((cur->height % 4) || (cur->width % 4))
-        return fail(ME_E_UNSUPPORTED, "me_cnn_pool: frame sides must be divisible by 4");
-    hipError_t e = launch_pool(ref->data, ref->pitch, cur->data, cur->pitch, cur->height / 4, cur->width / 4, x,
+    if ((cur->height % 8) || (cur->width % 8))
+        return fail(ME_E_UNSUPPORTED, "me_cnn_pool: frame sides must be divisible by 8");
+    hipError_t e = launch_pool(ref->data, ref->pitch, cur->data, cur->pitch, cur->height / 8, cur->width / 8, x,
                                reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "me_cnn_pool: launch");
     return ME_OK;
@@ -332,8 +332,6 @@ me_status check_layer(me_ctx ctx, int l, const void* a, const void* b, int n, in
     if (!ctx->cnn.loaded) return fail(ME_E_STATE, "proposal network: no parameters set");
     return ME_OK;
 }
-
-int out_dim(int l, int n) { return l < 3 ? (n + 1) / 2 : n; }
 
 }  // namespace
 }  // namespace me

@@ -460,18 +460,22 @@ def cnn_get_params(ctx: Context):
 
 
 def cnn_pool(ctx, ref, cur, x=None, stream=None):
-    """Network input [H/4, W/4, 8] bfloat16 of one frame pair."""
+    """Network input [H/8, W/8, 8] bfloat16 of one frame pair."""
     H, W = cur.shape
     if x is None:
-        x = torch.empty((H // 4, W // 4, 8), dtype=torch.bfloat16, device=cur.device)
+        x = torch.empty((H // 8, W // 8, 8), dtype=torch.bfloat16, device=cur.device)
     fr, fc = frame_of(ref), frame_of(cur)
     _check(_me_cnn_pool(_ctx_handle(ctx), ctypes.byref(fr), ctypes.byref(fc), x.data_ptr(), _stream_handle(stream)))
     return x
 
 
+CNN_STRIDES = (2, 2, 1, 1)
+
+
 def _out_grid(Hq, Wq):
-    for _ in range(3):
-        Hq, Wq = (Hq + 1) // 2, (Wq + 1) // 2
+    """Output grid of the proposal network on a [Hq, Wq] input."""
+    for s in CNN_STRIDES:
+        Hq, Wq = -(-Hq // s), -(-Wq // s)
     return Hq, Wq
 
 

@@ -302,3 +302,16 @@ def test_stats_validation(me):
     assert me._me_fallback_weight(FAKE, 1, 16, 1080, 1920, 1.5, 1.0, 0, None) == 1
     assert me._me_fallback_weight(FAKE, 1, 16, 1080, 1920, -1.0, 1.0, FAKE, None) == 1
     assert me._me_fallback_weight(FAKE, 1, 16, 1080, 1920, 1.5, float("nan"), FAKE, None) == 1
+
+
+@pytest.mark.parametrize("H,W", [(1080, 1920), (2160, 3840), (256, 256), (152, 216), (480, 640), (720, 1280)])
+def test_network_grid_is_block_grid(me, H, W):
+    """The binding's network output grid on the [H/8, W/8] input equals the
+    16x16 block grid and the oracle network's output size."""
+    from oracle import cnn
+
+    h, w = H // 8, W // 8
+    for _, _, s in cnn.LAYERS:
+        h, w = cnn.out_size(h, s), cnn.out_size(w, s)
+    assert me._out_grid(H // 8, W // 8) == me.block_grid(H, W, 16) == (h, w)
+    assert tuple(s for _, _, s in cnn.LAYERS) == me.CNN_STRIDES

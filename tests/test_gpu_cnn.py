@@ -300,9 +300,9 @@ def test_training_is_deterministic_and_resumable(dev, ctx):
 # the forward takes the unsplit kernel (one wave per 16 output pixels), and
 # beyond 256 chunks of 64 output pixels each weight-gradient workgroup walks
 # several chunks before its partial is reduced.  (layer, n, H, W) below give
-# 1519, 1148, 1148 and 1052 forward tiles, and 1013, 383, 287 and 287 chunks.
-FULL_FWD = [(0, 3, 270, 480), (1, 9, 135, 240), (2, 36, 68, 120), (3, 33, 34, 60)]
-FULL_BWD = [(0, 2, 270, 480), (1, 3, 135, 240), (2, 9, 68, 120), (3, 9, 34, 60)]
+# 1148, 1052, 1052 and 1052 forward tiles, and 383, 287, 287 and 287 chunks.
+FULL_FWD = [(0, 9, 135, 240), (1, 33, 68, 120), (2, 33, 34, 60), (3, 33, 34, 60)]
+FULL_BWD = [(0, 3, 135, 240), (1, 9, 68, 120), (2, 9, 34, 60), (3, 9, 34, 60)]
 
 
 @pytest.mark.parametrize("layer,n,H,W", FULL_FWD)

@@ -28,7 +28,7 @@ def dev():
 def loaded(dev):
     from paper_2508_05990_amd import train
 
-    params, median = train.load_weights(train.DEFAULT_WEIGHTS)
+    params, median, _ = train.load_weights(train.DEFAULT_WEIGHTS)
     ctx = dev.Context(0)
     dev.cnn_set_params(ctx, params, median)
     yield ctx, median

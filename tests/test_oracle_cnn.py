@@ -92,7 +92,7 @@ def test_conv_grads_match_autograd(s):
 def _tiny_batch(seed, H=32, W=48):
     rng = np.random.default_rng(seed)
     x = rng.normal(0, 0.5, size=(8, H, W))
-    bh, bw = -(-H // 8), -(-W // 8)
+    bh, bw = -(-H // 4), -(-W // 4)           # total stride 4
     mv = rng.integers(-6, 7, size=(bh, bw, 2))
     return x, mv
 
@@ -150,7 +150,7 @@ def test_berhu_and_bce():
     c = cnn.BERHU_C
     assert cnn.berhu(c) == pytest.approx(c) and cnn.berhu(c + 1e-12) == pytest.approx(c)   # continuous at c
     assert cnn.berhu(2 * c) == pytest.approx(((2 * c) ** 2 + c * c) / (2 * c))
-    for x in [-0.5, -0.1, 0.05, 0.3]:
+    for x in [-2.5 * c, -0.5 * c, -0.1 * c, 0.05 * c, 0.3 * c, 1.7 * c]:   # both branches
         fd = (cnn.berhu(x + 1e-7) - cnn.berhu(x - 1e-7)) / 2e-7
         assert cnn.berhu_grad(x) == pytest.approx(fd, rel=1e-5)
     for z in [-30.0, -2.0, 0.0, 1.5, 40.0]:
@@ -196,16 +196,42 @@ def test_cosine_schedule():
 def test_pool_input():
     P = np.full((4, 8, 12), 3072, np.uint16)
     x = cnn.pool_input(P, P)
-    assert x.shape == (8, 4, 6) and np.all(x == 1.0)
-    P2 = np.zeros((4, 2, 2), np.uint16)
+    assert x.shape == (8, 2, 3) and np.all(x == 1.0)
+    P2 = np.zeros((4, 4, 8), np.uint16)
     P2[:, 0, 0] = 4095
+    P2[2, 3, 7] = 1600
     x2 = cnn.pool_input(P2, P2, cnn.identity)
-    assert x2[0, 0, 0] == pytest.approx((4095 / 4 - 2048) / 1024)
+    assert x2.shape == (8, 1, 2)
+    assert x2[0, 0, 0] == pytest.approx((4095 / 16 - 2048) / 1024)
+    assert x2[1, 0, 1] == pytest.approx(-2.0)
+    assert x2[6, 0, 1] == pytest.approx((1600 / 16 - 2048) / 1024)
+
+
+def test_pool_input_from_mosaic_by_loops():
+    """Each input value is the mean of the 16 mosaic samples of its colour in
+    an 8x8 mosaic cell, written as loops over the mosaic itself."""
+    import oracle
+
+    rng = np.random.default_rng(3)
+    m0 = rng.integers(0, 4096, (16, 24), dtype=np.uint16)
+    m1 = rng.integers(0, 4096, (16, 24), dtype=np.uint16)
+    x = cnn.pool_input(oracle.pack_planes(m0), oracle.pack_planes(m1), cnn.identity)
+    assert x.shape == (8, 2, 3)
+    for f, m in enumerate((m0, m1)):
+        for c in range(4):
+            for y in range(2):
+                for xx in range(3):
+                    s = 0
+                    for r in range(8 * y, 8 * y + 8):
+                        for q in range(8 * xx, 8 * xx + 8):
+                            if r % 2 == c >> 1 and q % 2 == c & 1:
+                                s += int(m[r, q])
+                    assert x[4 * f + c, y, xx] == pytest.approx((s / 16 - 2048) / 1024, abs=1e-12)
 
 
 def test_output_grid_matches_block_grid():
     for Hp, Wp in [(540, 960), (1080, 1920), (360, 640), (240, 320)]:
-        h, w = Hp // 2, Wp // 2
+        h, w = Hp // 4, Wp // 4
         for _, _, s in cnn.LAYERS:
             h, w = cnn.out_size(h, s), cnn.out_size(w, s)
         assert (h, w) == (-(-Hp // 16), -(-Wp // 16))
