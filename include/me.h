@@ -287,8 +287,18 @@ me_status me_cnn_set_params(me_ctx ctx, const float* params, int32_t count, floa
 me_status me_cnn_get_params(me_ctx ctx, float* params, int32_t count, float* median_per_sample);
 /* Network input of one frame pair into x (device bfloat16 [H/8][W/8][8]). */
 me_status me_cnn_pool(me_ctx ctx, const me_frame* ref, const me_frame* cur, uint16_t* x, void* stream);
-/* Forward of n pooled inputs x ([n][Hq][Wq][8]) into out (device float32 [n][3][bh][bw]). */
+/* Forward of n pooled inputs x ([n][Hq][Wq][8]) into out (device float32 [n][3][bh][bw]),
+ * all four layers in one launch with the activations in LDS (the path
+ * me_estimate's proposal mode takes).  Each output takes its products in the
+ * order of the layer-by-layer kernels of the training step, so the two agree
+ * bit for bit.
+ * me_cnn_forward_acts: the same launch, also storing the activations of
+ * layers 0, 1, 2 (device bfloat16 [n][h1][w1][32], [n][h2][w2][32],
+ * [n][h2][w2][32]; h1 = ceil(Hq/2), h2 = ceil(h1/2), 16-byte aligned) for
+ * checking each layer on its own. */
 me_status me_cnn_forward(me_ctx ctx, const uint16_t* x, int32_t n, int32_t Hq, int32_t Wq, float* out, void* stream);
+me_status me_cnn_forward_acts(me_ctx ctx, const uint16_t* x, int32_t n, int32_t Hq, int32_t Wq, float* out,
+                              uint16_t* a0, uint16_t* a1, uint16_t* a2, void* stream);
 /*
  * One training step on n pooled inputs and their full-search vectors mv
  * (device int16 [n][bh][bw][2]): forward, loss (mean over the n x bh x bw

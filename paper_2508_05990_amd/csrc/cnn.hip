@@ -271,6 +271,208 @@ __global__ __launch_bounds__(256) void conv_fwd_split_kernel(const uint16_t* __r
     }
 }
 
+// ------------------------------------------------- whole-network forward --
+
+// Inference forward of all four layers in one launch.  A workgroup owns a
+// tile of FTY x FTX output blocks of one image and works backwards to the
+// regions each layer needs (zero padding 1 at every layer): layer 2 outputs
+// (FTY + 2) x (FTX + 2), layer 1 (FTY + 4) x (FTX + 4), layer 0 twice that plus
+// one, the pooled input twice that plus one; all of them live in LDS,
+// channels last (pixel strides padded against bank conflicts), with positions
+// outside a layer's grid stored as zero (the next layer's padding).  Each layer is an implicit GEMM on MFMA whose work
+// items are (16-pixel tile, 16-channel group) pairs dealt to the eight waves;
+// every output takes the k-steps in order and the bias, ReLU and bfloat16
+// rounding of conv_fwd_kernel, so the result equals the layer-by-layer
+// chain of that kernel bit for bit.  ACTS: also store each layer's
+// activations over the tile's own region (every position is owned by one
+// tile), in the layer kernels' layouts.
+constexpr int FTY = 2, FTX = 4;                              // output blocks per workgroup
+constexpr int FNW = 8;                                       // waves per workgroup
+// LDS pixel strides (bfloat16 elements, multiples of 4 for 8-byte reads),
+// padded so that a wave's 16 pixels of one B-operand read fall on distinct
+// banks: the reader of s_in and s_0 steps two pixels per lane (stride 2),
+// the readers of s_1 and s_2 one pixel.
+constexpr int PIN = 12, P0 = 36, P1 = 40, P2 = 40;
+constexpr int F2Y = FTY + 2, F2X = FTX + 2;                  // layer 2 outputs needed
+constexpr int F1Y = FTY + 4, F1X = FTX + 4;                  // layer 1 outputs
+constexpr int F0Y = 2 * F1Y + 1, F0X = 2 * F1X + 1;          // layer 0 outputs
+constexpr int FIY = 2 * F0Y + 1, FIX = 2 * F0X + 1;          // pooled input
+
+// Layer of CIN -> COUT (ReLU, bfloat16) from an LDS region [.][IX][CIN] to an
+// LDS region [OY][OX][COUT]: output (ly, lx) reads input (S ly + ky, S lx + kx).
+// (gy0, gx0): grid position of output (0, 0); outputs outside [0, Ho) x [0, Wo)
+// are stored as zero.
+// The A operands of every k-step of 16-channel group t of a layer (KS steps)
+// and the lane's four output-channel biases, requested before the barrier
+// that precedes the layer so that their latency overlaps the wait.
+template <int KS>
+__device__ __forceinline__ void fused_operands(const uint16_t* __restrict__ wp, const float* __restrict__ bias, int t,
+                                               int lane, uint2 (&av)[KS], float (&bb)[4])
+{
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) av[ks] = reinterpret_cast<const uint2*>(wp)[(t * KS + ks) * 64 + lane];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bb[i] = bias ? bias[t * 16 + 4 * (lane >> 4) + i] : 0.f;
+}
+
+template <int CIN, int COUT, int S, int IX, int IP, int OY, int OX, int OP>
+__device__ __forceinline__ void fused_layer(const uint16_t* in_l, uint16_t* out_l, const uint2 (&av)[(9 * CIN + 15) / 16],
+                                            const float (&bb)[4], int gy0, int gx0, int Ho, int Wo, int w, int lane)
+{
+    constexpr int K = 9 * CIN, KS = (K + 15) / 16, MT = (COUT + 15) / 16;
+    static_assert(MT == 2, "two 16-channel groups: wave w keeps group w % 2");
+    constexpr int NP = OY * OX, PT = (NP + 15) / 16;
+    const int g = lane >> 4;
+    const int t = w & 1;
+    for (int pt = w >> 1; pt < PT; pt += FNW / 2) {
+        const int p = pt * 16 + (lane & 15);
+        const bool valid = p < NP;
+        const int ly = valid ? p / OX : 0, lx = valid ? p - (p / OX) * OX : 0;
+        uint2 bv[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int k0 = ks * 16 + 4 * g;
+            bv[ks] = make_uint2(0u, 0u);
+            if (k0 < K) {
+                const int tap = k0 / CIN, c = k0 - tap * CIN;
+                const int iy = S * ly + tap / 3, ix = S * lx + tap % 3;
+                bv[ks] = *reinterpret_cast<const uint2*>(in_l + (iy * IX + ix) * IP + c);
+            }
+        }
+        v4f32 acc = (v4f32){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) acc = mfma(as_v4(av[ks]), as_v4(bv[ks]), acc);
+        if (valid) {
+            const int o0 = t * 16 + 4 * g;
+            const int gy = gy0 + ly, gx = gx0 + lx;
+            const bool inside = gy >= 0 && gy < Ho && gx >= 0 && gx < Wo;
+            float v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i] = inside ? fmaxf(acc[i] + bb[i], 0.f) : 0.f;
+            *reinterpret_cast<uint2*>(out_l + (ly * OX + lx) * OP + o0) = pack4(v[0], v[1], v[2], v[3]);
+        }
+    }
+}
+
+// Copy the rows [r0, r0 + ny) x columns [c0, c0 + nx) of an LDS region
+// [.][LX][32] (grid position of local (0, 0): (gy0, gx0)) to the global
+// [Ho][Wo][32] map, positions inside the grid only.
+__device__ __forceinline__ void fused_store_acts(const uint16_t* l, int LX, int LP, int r0, int c0, int ny, int nx, int gy0,
+                                                 int gx0, uint16_t* __restrict__ g, int Ho, int Wo, int tid)
+{
+    for (int e = tid; e < ny * nx * 4; e += FNW * 64) {
+        const int q = e & 3, pix = e >> 2;                   // 8 channels (16 bytes) per element
+        const int y = r0 + pix / nx, x = c0 + pix % nx;
+        const int gy = gy0 + y, gx = gx0 + x;
+        if (gy < 0 || gy >= Ho || gx < 0 || gx >= Wo) continue;
+        const uint2* sp = reinterpret_cast<const uint2*>(l + (y * LX + x) * LP + 8 * q);   // 8-byte aligned
+        const uint2 lo = sp[0], hi = sp[1];
+        *reinterpret_cast<uint4*>(g + ((size_t)gy * Wo + gx) * 32 + 8 * q) = make_uint4(lo.x, lo.y, hi.x, hi.y);
+    }
+}
+
+// Eight waves per workgroup, at most two workgroups per CU (four waves per
+// SIMD): registers up to that occupancy keep every A operand of a layer in
+// VGPRs.
+template <bool ACTS>
+__global__ __launch_bounds__(FNW * 64) __attribute__((amdgpu_waves_per_eu(1, 4))) void cnn_fused_kernel(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wf,
+                                                        const float* __restrict__ params, float* __restrict__ out,
+                                                        int Hq, int Wq, int H1, int W1, int H2, int W2, int tiles_x,
+                                                        int tiles_img, int off1, int off2, int off3,
+                                                        uint16_t* __restrict__ a0, uint16_t* __restrict__ a1,
+                                                        uint16_t* __restrict__ a2)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t s_in[FIY * FIX * PIN];
+    __shared__ __attribute__((aligned(16))) uint16_t s_0[F0Y * F0X * P0];
+    __shared__ __attribute__((aligned(16))) uint16_t s_1[F1Y * F1X * P1];
+    __shared__ __attribute__((aligned(16))) uint16_t s_2[F2Y * F2X * P2];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    // neighbouring tiles share input rows: contiguous tile ranges per XCD
+    const int nwg = gridDim.x, xcd = blockIdx.x & 7, kq = blockIdx.x >> 3;
+    const int wg = xcd * (nwg >> 3) + min(xcd, nwg & 7) + kq;
+    const int img = wg / tiles_img, tt = wg - img * tiles_img;
+    const int by0 = (tt / tiles_x) * FTY, bx0 = (tt % tiles_x) * FTX;
+    // grid positions of local (0, 0) per layer
+    const int y2 = by0 - 1, x2 = bx0 - 1, y1 = by0 - 2, x1 = bx0 - 2;
+    const int y0 = 2 * y1 - 1, x0 = 2 * x1 - 1, yi = 2 * y0 - 1, xi = 2 * x0 - 1;
+
+    const int t = w & 1;
+    uint2 av0[5];
+    float bb0[4];
+    fused_operands<5>(wf, params + 2304, t, lane, av0, bb0);
+    // pooled input: every load of the thread in flight before the LDS writes
+    const uint16_t* src = in + (size_t)img * Hq * Wq * 8;
+    constexpr int NIN = (FIY * FIX + FNW * 64 - 1) / (FNW * 64);
+    uint4 vin[NIN];
+#pragma unroll
+    for (int r = 0; r < NIN; ++r) {
+        const int e = tid + r * FNW * 64;
+        const int y = e / FIX, x = e - (e / FIX) * FIX;
+        const int gy = yi + y, gx = xi + x;
+        vin[r] = make_uint4(0u, 0u, 0u, 0u);
+        if (e < FIY * FIX && gy >= 0 && gy < Hq && gx >= 0 && gx < Wq)
+            vin[r] = *reinterpret_cast<const uint4*>(src + ((size_t)gy * Wq + gx) * 8);
+    }
+#pragma unroll
+    for (int r = 0; r < NIN; ++r) {
+        const int e = tid + r * FNW * 64;
+        if (e < FIY * FIX) {
+            *reinterpret_cast<uint2*>(s_in + e * PIN) = make_uint2(vin[r].x, vin[r].y);
+            *reinterpret_cast<uint2*>(s_in + e * PIN + 4) = make_uint2(vin[r].z, vin[r].w);
+        }
+    }
+    __syncthreads();
+    fused_layer<8, 32, 2, FIX, PIN, F0Y, F0X, P0>(s_in, s_0, av0, bb0, y0, x0, H1, W1, w, lane);
+    uint2 av1[18];
+    float bb1[4];
+    fused_operands<18>(wf + off1, params + 11552, t, lane, av1, bb1);
+    __syncthreads();
+    fused_layer<32, 32, 2, F0X, P0, F1Y, F1X, P1>(s_0, s_1, av1, bb1, y1, x1, H2, W2, w, lane);
+    uint2 av2[18];
+    float bb2[4];
+    fused_operands<18>(wf + off2, params + 20800, t, lane, av2, bb2);
+    __syncthreads();
+    fused_layer<32, 32, 1, F1X, P1, F2Y, F2X, P2>(s_1, s_2, av2, bb2, y2, x2, H2, W2, w, lane);
+    // layer 3's A operands (one 16-channel group, wave 0), before the barrier
+    uint2 av3[18];
+    float bb3[4];
+    if (w == 0) fused_operands<18>(wf + off3, nullptr, 0, lane, av3, bb3);
+    __syncthreads();
+    if (ACTS) {
+        uint16_t* g0 = a0 + (size_t)img * H1 * W1 * 32;
+        uint16_t* g1 = a1 + (size_t)img * H2 * W2 * 32;
+        uint16_t* g2 = a2 + (size_t)img * H2 * W2 * 32;
+        fused_store_acts(s_0, F0X, P0, 2 * by0 - y0, 2 * bx0 - x0, 2 * FTY, 2 * FTX, y0, x0, g0, H1, W1, tid);
+        fused_store_acts(s_1, F1X, P1, by0 - y1, bx0 - x1, FTY, FTX, y1, x1, g1, H2, W2, tid);
+        fused_store_acts(s_2, F2X, P2, by0 - y2, bx0 - x2, FTY, FTX, y2, x2, g2, H2, W2, tid);
+    }
+    // layer 3 (32 -> 3, no ReLU, float32 [3][H2][W2]): one 16-pixel tile, wave 0
+    if (w != 0) return;
+    constexpr int K = 9 * 32, KS = K / 16;
+    const int g = lane >> 4;
+    const int p = lane & 15;
+    const bool valid = p < FTY * FTX;
+    const int ly = valid ? p / FTX : 0, lx = valid ? p % FTX : 0;
+    uint2 bv[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const int k0 = ks * 16 + 4 * g;
+        const int tap = k0 / 32, c = k0 - tap * 32;
+        bv[ks] = *reinterpret_cast<const uint2*>(s_2 + ((ly + tap / 3) * F2X + lx + tap % 3) * P2 + c);
+    }
+    v4f32 acc = (v4f32){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) acc = mfma(as_v4(av3[ks]), as_v4(bv[ks]), acc);
+    const int by = by0 + ly, bx = bx0 + lx;
+    if (!valid || by >= H2 || bx >= W2) return;
+    const float* b3 = params + 21696;
+    float* o = out + (size_t)img * 3 * H2 * W2 + (size_t)by * W2 + bx;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (4 * g + i < 3) o[(size_t)(4 * g + i) * H2 * W2] = acc[i] + b3[4 * g + i];
+}
+
 // ------------------------------------------------------------------ loss --
 
 __device__ __forceinline__ float berhu(float x, float c) { const float a = fabsf(x); return a <= c ? a : (x * x + c * c) / (2.f * c); }
@@ -472,24 +674,38 @@ __global__ __launch_bounds__(256) void conv_wgrad_kernel(const uint16_t* __restr
     if (tid < COUT) partial[(size_t)gridDim.x * COUT * K + (size_t)blockIdx.x * COUT + tid] = bacc;
 }
 
-// grads (flat layout: W[o][c][ky][kx] then b[o]) = sum over workgroups of the
-// partials, in workgroup order.
-__global__ void wgrad_reduce_kernel(const float* __restrict__ partial, int nwg, int cin, int cout, int off_w,
-                                    int off_b, float* __restrict__ grads)
+// grads (flat layout: W[o][c][ky][kx] then b[o]) = fixed-order sum of the nwg
+// per-workgroup partials of every weight and bias gradient: 64 outputs per
+// workgroup; wave q sums partials q, q + 4, q + 8, ...
+// in ascending order (independent loads, many in flight), then wave 0 adds
+// the four sums in wave order.  The order never depends on timing, so the
+// same inputs give the same bits.
+__global__ __launch_bounds__(256) void wgrad_reduce_kernel(const float* __restrict__ partial, int nwg, int cin,
+                                                           int cout, int off_w, int off_b, float* __restrict__ grads)
 {
-    const int K = 9 * cin;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < cout * K) {
+    __shared__ float part[3][64];
+    const int K = 9 * cin, nw = cout * K, m = nw + cout;
+    const int j = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + j;
+    float s = 0.f;
+    if (e < m) {
+        const float* src = e < nw ? partial + e : partial + (size_t)nwg * nw + (e - nw);
+        const size_t stride = e < nw ? (size_t)nw : (size_t)cout;
+#pragma unroll 8
+        for (int w = q; w < nwg; w += 4) s += src[(size_t)w * stride];
+    }
+    if (q > 0) part[q - 1][j] = s;
+    __syncthreads();
+    if (q != 0 || e >= m) return;
+    s = s + part[0][j];
+    s = s + part[1][j];
+    s = s + part[2][j];
+    if (e < nw) {
         const int o = e / K, k = e - o * K;
-        float s = 0.f;
-        for (int w = 0; w < nwg; ++w) s += partial[(size_t)w * cout * K + e];
         const int tap = k / cin, c = k - tap * cin;
         grads[off_w + (o * cin + c) * 9 + tap] = s;
-    } else if (e < cout * K + cout) {
-        const int o = e - cout * K;
-        float s = 0.f;
-        for (int w = 0; w < nwg; ++w) s += partial[(size_t)nwg * cout * K + (size_t)w * cout + o];
-        grads[off_b + o] = s;
+    } else {
+        grads[off_b + (e - nw)] = s;
     }
 }
 
@@ -563,6 +779,24 @@ hipError_t launch_conv_fwd(int l, const uint16_t* in, const uint16_t* wp, const 
     return hipGetLastError();
 }
 
+hipError_t launch_cnn_fused(const uint16_t* in, const uint16_t* wf, const float* params, float* out, int n, int Hq,
+                            int Wq, uint16_t* a0, uint16_t* a1, uint16_t* a2, hipStream_t st)
+{
+    const int H1 = (Hq + 1) / 2, W1 = (Wq + 1) / 2, H2 = (H1 + 1) / 2, W2 = (W1 + 1) / 2;
+    const int tiles_x = div_up(W2, FTX), tiles_img = div_up(H2, FTY) * tiles_x;
+    const long long nwg = (long long)n * tiles_img;
+    if (nwg <= 0 || nwg > 0x7fffffffLL) return hipErrorInvalidValue;
+    const int off1 = packed_fwd(kCin[0], kCout[0]), off2 = off1 + packed_fwd(kCin[1], kCout[1]);
+    const int off3 = off2 + packed_fwd(kCin[2], kCout[2]);
+    if (a0)
+        hipLaunchKernelGGL(cnn_fused_kernel<true>, dim3((unsigned)nwg), dim3(FNW * 64), 0, st, in, wf, params, out, Hq, Wq,
+                           H1, W1, H2, W2, tiles_x, tiles_img, off1, off2, off3, a0, a1, a2);
+    else
+        hipLaunchKernelGGL(cnn_fused_kernel<false>, dim3((unsigned)nwg), dim3(FNW * 64), 0, st, in, wf, params, out, Hq,
+                           Wq, H1, W1, H2, W2, tiles_x, tiles_img, off1, off2, off3, a0, a1, a2);
+    return hipGetLastError();
+}
+
 hipError_t launch_loss(const float* out, const int16_t* mv, const float* wt, int n, int nblk, int R, int rr,
                        uint16_t* dz, float* bl, float* loss, hipStream_t st)
 {
@@ -614,7 +848,7 @@ hipError_t launch_conv_wgrad(int l, const uint16_t* x, const uint16_t* dz, float
     default: return hipErrorInvalidValue;
     }
     const int m = cout[l] * 9 * cin[l] + cout[l];
-    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(div_up(m, 256)), dim3(256), 0, st, partial, nwg, cin[l], cout[l],
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(div_up(m, 64)), dim3(256), 0, st, partial, nwg, cin[l], cout[l],
                        offw[l], offb[l], grads);
     return hipGetLastError();
 }

@@ -148,7 +148,9 @@ me_status cnn_propose(me_ctx ctx, const me_frame* ref, const me_frame* cur, hipS
     CnnState& c = ctx->cnn;
     hipError_t e = launch_pool(ref->data, ref->pitch, cur->data, cur->pitch, Hq, Wq, c.a0, st);
     if (e != hipSuccess) return hip_fail(e, "proposal network: pool launch");
-    return forward_impl(ctx, c.a0, 1, Hq, Wq, c.out, st);
+    e = launch_cnn_fused(c.a0, c.wf, c.params, c.out, 1, Hq, Wq, nullptr, nullptr, nullptr, st);
+    if (e != hipSuccess) return hip_fail(e, "proposal network: forward launch");
+    return ME_OK;
 }
 
 }  // namespace me
@@ -212,9 +214,24 @@ me_status me_cnn_forward(me_ctx ctx, const uint16_t* x, int32_t n, int32_t Hq, i
     me_status s = check_net_input(ctx, x, n, Hq, Wq);
     if (s != ME_OK) return s;
     if (!out) return fail(ME_E_INVAL, "me_cnn_forward: null output");
-    s = ensure_acts(ctx, n, Hq, Wq);
+    hipError_t e = launch_cnn_fused(x, ctx->cnn.wf, ctx->cnn.params, out, n, Hq, Wq, nullptr, nullptr, nullptr,
+                                    reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "me_cnn_forward: launch");
+    return ME_OK;
+}
+
+me_status me_cnn_forward_acts(me_ctx ctx, const uint16_t* x, int32_t n, int32_t Hq, int32_t Wq, float* out,
+                              uint16_t* a0, uint16_t* a1, uint16_t* a2, void* stream)
+{
+    me_status s = check_net_input(ctx, x, n, Hq, Wq);
     if (s != ME_OK) return s;
-    return forward_impl(ctx, x, n, Hq, Wq, out, reinterpret_cast<hipStream_t>(stream));
+    if (!out || !a0 || !a1 || !a2) return fail(ME_E_INVAL, "me_cnn_forward_acts: null output");
+    if ((reinterpret_cast<uintptr_t>(a0) | reinterpret_cast<uintptr_t>(a1) | reinterpret_cast<uintptr_t>(a2)) & 15u)
+        return fail(ME_E_INVAL, "me_cnn_forward_acts: activations must be 16-byte aligned");
+    hipError_t e = launch_cnn_fused(x, ctx->cnn.wf, ctx->cnn.params, out, n, Hq, Wq, a0, a1, a2,
+                                    reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "me_cnn_forward_acts: launch");
+    return ME_OK;
 }
 
 me_status me_cnn_train_step(me_ctx ctx, const uint16_t* x, const int16_t* mv, const float* weight, int32_t n,

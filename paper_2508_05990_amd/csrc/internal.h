@@ -157,7 +157,7 @@ hipError_t launch_fallback(const float* out, const int32_t* sad, int bh, int bw,
                            hipStream_t stream);
 
 // Proposal network (cnn.hip).  Layer l = 0..3: (cin, cout, stride) =
-// (8,32,2), (32,32,2), (32,32,2), (32,3,1).
+// (8,32,2), (32,32,2), (32,32,1), (32,3,1).
 constexpr int kCnnParams = 21699;
 int cnn_fwd_packed_size(int l);
 int cnn_bwd_packed_size(int l);
@@ -168,6 +168,11 @@ hipError_t launch_pool(const uint16_t* ref, int64_t ref_pitch, const uint16_t* c
 hipError_t launch_pack(const float* w, uint16_t* fwd, uint16_t* bwd, hipStream_t st);
 hipError_t launch_conv_fwd(int l, const uint16_t* in, const uint16_t* wp, const float* bias, void* out, int n, int H,
                            int W, int Ho, int Wo, hipStream_t st);
+// The four layers in one launch for inference (activations in LDS); the same
+// products in the same order as conv_fwd_kernel, so the same bits.  a0..a2
+// (optional, all or none) receive the layer 0..2 activations.
+hipError_t launch_cnn_fused(const uint16_t* in, const uint16_t* wf, const float* params, float* out, int n, int Hq,
+                            int Wq, uint16_t* a0, uint16_t* a1, uint16_t* a2, hipStream_t st);
 hipError_t launch_loss(const float* out, const int16_t* mv, const float* wt, int n, int nblk, int R, int rr,
                        uint16_t* dz, float* bl, float* loss, hipStream_t st);
 hipError_t launch_conv_dgrad(int l, const uint16_t* dz, const uint16_t* wb, const uint16_t* aprev, uint16_t* dprev,

@@ -87,6 +87,7 @@ _me_cnn_set_params = _sig("me_cnn_set_params", [_P, _P, _I32, _F])
 _me_cnn_get_params = _sig("me_cnn_get_params", [_P, _P, _I32, _P])
 _me_cnn_pool = _sig("me_cnn_pool", [_P, ctypes.POINTER(MeFrame), ctypes.POINTER(MeFrame), _P, _P])
 _me_cnn_forward = _sig("me_cnn_forward", [_P, _P, _I32, _I32, _I32, _P, _P])
+_me_cnn_forward_acts = _sig("me_cnn_forward_acts", [_P, _P, _I32, _I32, _I32, _P, _P, _P, _P, _P])
 _me_cnn_train_step = _sig("me_cnn_train_step", [_P, _P, _P, _P, _I32, _I32, _I32, _I32, _I32, _F, _I32, _P, _P, _P])
 _me_cnn_state_bytes = _sig("me_cnn_state_bytes", [], ctypes.c_int64)
 _me_cnn_save_state = _sig("me_cnn_save_state", [_P, _P, ctypes.c_int64])
@@ -487,6 +488,19 @@ def cnn_forward(ctx, x, out=None, stream=None):
         out = torch.empty((n, 3, bh, bw), dtype=torch.float32, device=x.device)
     _check(_me_cnn_forward(ctx.handle, x.data_ptr(), n, Hq, Wq, out.data_ptr(), _stream_handle(stream)))
     return out
+
+
+def cnn_forward_acts(ctx, x, stream=None):
+    """Whole-network forward that also returns the layer 0-2 activations:
+    (out [n, 3, bh, bw] float32, [a0 [n, h1, w1, 32], a1, a2] bfloat16)."""
+    n, Hq, Wq, _ = x.shape
+    h1, w1 = -(-Hq // 2), -(-Wq // 2)
+    h2, w2 = -(-h1 // 2), -(-w1 // 2)
+    out = torch.empty((n, 3, h2, w2), dtype=torch.float32, device=x.device)
+    acts = [torch.empty((n, h, w, 32), dtype=torch.bfloat16, device=x.device) for h, w in ((h1, w1), (h2, w2), (h2, w2))]
+    _check(_me_cnn_forward_acts(ctx.handle, x.data_ptr(), n, Hq, Wq, out.data_ptr(), acts[0].data_ptr(),
+                                acts[1].data_ptr(), acts[2].data_ptr(), _stream_handle(stream)))
+    return out, acts
 
 
 def cnn_train_step(ctx, x, mv, radius=32, refine_radius=2, lr=1e-4, update=True, grads=None, loss=None,

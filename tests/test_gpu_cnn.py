@@ -380,3 +380,45 @@ def test_layer_backward_many_chunks(dev, ctx, layer, n, H, W):
             ref = cnn.conv_dgrad(d[i], Wr, s, x[i].shape) * (x[i] > 0)
             ab = cnn.conv_dgrad(np.abs(d[i]), np.abs(Wr), s, x[i].shape)
             assert (np.abs(got[i] - ref) <= U * np.abs(ref) + 2e-5 * ab + 1e-30).all(), i
+
+
+@pytest.mark.parametrize("n,Hq,Wq", [(9, 135, 240), (2, 19, 27), (1, 3, 5), (3, 1, 2)])
+def test_fused_forward_each_layer(dev, ctx, n, Hq, Wq):
+    """The one-launch forward (me_cnn_forward, the proposal mode's network)
+    with its activations stored: each layer element by element against the
+    oracle layer fed the kernel's own previous activation, at the bounds of
+    test_layer_forward; full tiles, ragged tiles and grids smaller than one
+    tile.  At 9 x 135 x 240 layer 0 runs the unsplit layer kernel in the
+    layer-by-layer path, and the two paths agree bit for bit there."""
+    import torch
+
+    params = _params(13)
+    dev.cnn_set_params(ctx, params, 1.0)
+    rng = np.random.default_rng(300 + Hq)
+    x = cnn.bf16_round(rng.normal(0, 1, (n, 8, Hq, Wq)))
+    xt = _bf(_nhwc(x))
+    print("fused forward on %d x %dx%d" % (n, Hq, Wq), flush=True)
+    out, acts = dev.cnn_forward_acts(ctx, xt)
+    plain = dev.cnn_forward(ctx, xt)
+    torch.cuda.synchronize()
+    assert torch.equal(out, plain)                           # the stores change nothing
+    layers = cnn.unpack(params)
+    prev = x
+    for l in range(4):
+        ci, co, s = cnn.LAYERS[l]
+        Wl, bl = layers[l]
+        Wr = cnn.bf16_round(Wl)
+        got = _nchw(_np(acts[l])) if l < 3 else _np(out)
+        for i in range(n):
+            z = cnn.conv3x3(prev[i], Wr, bl, s)
+            ab = cnn.conv3x3_abs(prev[i], Wr, bl, s)
+            ref = np.maximum(z, 0) if l < 3 else z
+            bound = (U * np.abs(ref) if l < 3 else 0) + 2e-5 * ab + 1e-30
+            assert got[i].shape == ref.shape, (l, got[i].shape, ref.shape)
+            assert (np.abs(got[i] - ref) <= bound).all(), (l, i, np.abs(got[i] - ref).max())
+        prev = got
+    if n * ((Hq + 1) // 2) * ((Wq + 1) // 2) >= 1024 * 64:
+        a0 = torch.empty_like(acts[0])
+        dev.cnn_layer_forward(ctx, 0, xt, a0)
+        torch.cuda.synchronize()
+        assert torch.equal(a0, acts[0])
