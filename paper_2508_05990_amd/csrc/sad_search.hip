@@ -151,7 +151,18 @@ __device__ __forceinline__ void tile_sads(cptr_t curp, int64_t cur_pitch, int h,
                                           int pitch4, uint32_t (&acc)[KY][KX])
 {
     constexpr int SEGV = (CW + KX - 1 + 3) / 4;
-    constexpr int KY2 = KY % 2 == 0 ? KY : 2 * KY;   // steps per unrolled group (even)
+    // Scalar and LDS loads share one wait counter and scalar loads return out
+    // of order, so any wait for an LDS read also waits for every scalar load
+    // in flight.  With KY >= 3 a step's loads are issued only after its first
+    // candidate row's SADs (whose wait then covers just the previous step's
+    // loads), and the slot of the tile's last candidate row, filled in the
+    // step that uses it, is waited for half a step after its request.  Shorter
+    // tiles keep the plain order (loads, then every row): a spare ring slot
+    // filled a step ahead cost more in registers than it saved in waits (4x2
+    // tiles at 4K R=64 and the batch queue measured slower).
+    constexpr bool REORDER = KY >= 3;
+    constexpr int RS = KY;                           // ring slots
+    constexpr int G = RS % 2 == 0 ? RS : 2 * RS;     // steps per unrolled group: whole ring turns, even
 #pragma unroll
     for (int j = 0; j < KY; ++j)
 #pragma unroll
@@ -164,7 +175,7 @@ __device__ __forceinline__ void tile_sads(cptr_t curp, int64_t cur_pitch, int h,
             const uint4* col4 = lbase4 + par * pitch4 + (q * CW) / 4;   // LDS row par, chunk q
             cptr_t ccol = curp + par * cur_pitch + q * CW;                 // block row par, chunk q
             const int64_t rstep = 2 * cur_pitch;
-            uint4 ring[KY][SEGV];
+            uint4 ring[RS][SEGV];                          // slot (r mod RS) holds LDS row 2 r + par
 #pragma unroll
             for (int t = 0; t < KY - 1; ++t)
 #pragma unroll
@@ -173,59 +184,56 @@ __device__ __forceinline__ void tile_sads(cptr_t curp, int64_t cur_pitch, int h,
 #pragma unroll
             for (int k = 0; k < CW; ++k) cA[k] = ccol[k];
             cptr_t nxt = ccol + rstep;                     // block row par + 2 (st + 1)
-            // step st (u = st mod KY2): SADs against block row cu; block row par + 2 (st + 1)
-            // into cx (the last step reloads row par, which is in the block)
-            // SADs of candidate row j of the tile against block row cu (ring slot (u + j) mod KY)
-            auto row_sads = [&](const int u, const int j, const uint32_t(&cu)[CW]) {
+            // step st (u = st mod G): SADs of candidate rows st .. st + KY - 1 against
+            // block row cu; block row par + 2 (st + 1) into cx (the last step rereads
+            // row par, which is in the block)
+            auto row_sads = [&](const int u, const int j, const uint32_t(&cu)[CW], const int k0, const int k1) {
                 uint32_t seg[SEGV * 4];
 #pragma unroll
                 for (int v = 0; v < SEGV; ++v) {
-                    const uint4 t4 = ring[(u + j) % KY][v];
+                    const uint4 t4 = ring[(u + j) % RS][v];
                     seg[4 * v + 0] = t4.x;
                     seg[4 * v + 1] = t4.y;
                     seg[4 * v + 2] = t4.z;
                     seg[4 * v + 3] = t4.w;
                 }
 #pragma unroll
-                for (int k = 0; k < CW; ++k)
+                for (int k = k0; k < k1; ++k)
 #pragma unroll
                     for (int i = 0; i < KX; ++i) acc[j][i] = __builtin_amdgcn_sad_u16(cu[k], seg[k + i], acc[j][i]);
             };
             auto loads = [&](const int u, const int st, uint32_t(&cx)[CW]) {
+                if (!REORDER)
+#pragma unroll
+                    for (int v = 0; v < SEGV; ++v) ring[(u + KY - 1) % RS][v] = col4[(2 * (st + KY - 1)) * pitch4 + v];
                 const cptr_t src = st + 1 < h ? nxt : ccol;
 #pragma unroll
                 for (int k = 0; k < CW; ++k) cx[k] = src[k];
                 nxt += rstep;
+                if (REORDER)
 #pragma unroll
-                for (int v = 0; v < SEGV; ++v) ring[(u + KY - 1) % KY][v] = col4[(2 * (st + KY - 1)) * pitch4 + v];
+                    for (int v = 0; v < SEGV; ++v) ring[(u + KY - 1) % RS][v] = col4[(2 * (st + KY - 1)) * pitch4 + v];
             };
             auto one = [&](const int u, const int st, const uint32_t(&cu)[CW], uint32_t(&cx)[CW]) {
-                if constexpr (KY >= 3) {
-                    // Scalar and LDS loads share one wait counter and scalar loads
-                    // return out of order, so any wait for an LDS read also waits
-                    // for every scalar load in flight.  Fixed order per step: the
-                    // first candidate row (its wait covers only the block row
-                    // requested a step earlier), then the next block row and the new
-                    // ring slot, then the rows held in registers, and only then the
-                    // row that needs the new slot, half a step after its request.
-                    row_sads(u, 0, cu);
-                    __builtin_amdgcn_sched_barrier(0);
+                if constexpr (!REORDER) {
                     loads(u, st, cx);
-                    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                    for (int j = 1; j < KY - 1; ++j) row_sads(u, j, cu);
-                    __builtin_amdgcn_sched_barrier(0);
-                    row_sads(u, KY - 1, cu);
+                    for (int j = 0; j < KY; ++j) row_sads(u, j, cu, 0, CW);
                 } else {
+                    row_sads(u, 0, cu, 0, CW);
+                    __builtin_amdgcn_sched_barrier(0);
                     loads(u, st, cx);
+                    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                    for (int j = 0; j < KY; ++j) row_sads(u, j, cu);
+                    for (int j = 1; j < KY - 1; ++j) row_sads(u, j, cu, 0, CW);
+                    __builtin_amdgcn_sched_barrier(0);
+                    row_sads(u, KY - 1, cu, 0, CW);
                 }
             };
 #pragma unroll 1
-            for (int step = 0; step < h; step += KY2) {
+            for (int step = 0; step < h; step += G) {
 #pragma unroll
-                for (int u = 0; u < KY2; ++u) {
+                for (int u = 0; u < G; ++u) {
                     const int st = step + u;               // block row par + 2 st
                     if (st < h) {
                         if (u & 1) one(u, st, cB, cA);
