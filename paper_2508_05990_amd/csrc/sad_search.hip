@@ -893,52 +893,65 @@ __device__ __forceinline__ uint32_t lds_rows_sad(const uint32_t* cl, int cp, con
 }
 
 // Stage searches with a small candidate window (radius <= 4, e.g. the refine
-// step of the proposal path): one wave per block, so a 5x5 window keeps most
-// lanes busy where a 4x4 tile per lane would keep one.  Each wave stages its
-// block's reference window and the block itself in its own LDS slice of
-// a.band_ty words and waits only for its own loads (no workgroup barrier,
-// four independent blocks per workgroup).  Lanes are (candidate, row slice)
-// pairs: with nc candidates the block's rows are cut into S slices, the
-// largest power of two with S * nc <= 64, and the slices' partial SADs are
-// added with a butterfly.
-// With a.net (the proposal path), the predictor of each block is decoded
-// from the network output in place.
+// step of the proposal path): one block per two waves, so a 5x5 window keeps
+// most lanes busy where a 4x4 tile per lane would keep one.  The block's rows
+// are split between the two waves; each wave stages its half's reference
+// window and current-block rows in its own LDS slice of a.band_ty words and
+// waits only for its own loads.  Lanes are (candidate, row slice) pairs: with
+// nc candidates the half's rows are cut into S slices, the largest power of
+// two with S * nc <= 64, and the slices' partial SADs are added with a
+// butterfly; the two halves' sums (integers, exact in any order) meet in LDS
+// and the first wave of the block takes the minimum key.  Two blocks per
+// workgroup.  With a.net (the proposal path), the predictor of each block is
+// decoded from the network output in place.
+constexpr int kSmallMaxCand = 81;              // (2 x 4 + 1)^2
 template <int CW, int NCH, bool BATCH>
 __global__ __launch_bounds__(256) void sad_small_kernel(SearchArgs a_in)
 {
     extern __shared__ uint4 lds_dyn[];
+    __shared__ uint32_t halves[2][2][kSmallMaxCand];   // [block slot][half][candidate]
     constexpr int B = CW * NCH;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    int blk;
+    const int bslot = wave >> 1, half = wave & 1;
+    int blk = 0;
+    bool active = true;
     SearchArgs a = a_in;
     if (BATCH) {
         const int nblk = a.bh * a.bw;
-        const int g = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
-        const int job = g / nblk;
-        if (job >= a.n_jobs) return;                  // this wave only: nothing below waits for others
-        blk = g - job * nblk;
-        a = for_job(a_in, job);
+        const int gb = xcd_remap(blockIdx.x, gridDim.x) * 2 + bslot;
+        const int job = gb / nblk;
+        active = job < a.n_jobs;
+        if (active) {
+            blk = gb - job * nblk;
+            a = for_job(a_in, job);
+        }
     } else if (a.list) {
-        const int slot = blockIdx.x * 4 + wave;
-        if (slot >= *a.list_n) return;
-        blk = a.list[slot];
+        const int slot = blockIdx.x * 2 + bslot;
+        active = slot < *a.list_n;
+        if (active) blk = a.list[slot];
     } else {
-        blk = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
-        if (blk >= a.bh * a.bw) return;
+        blk = xcd_remap(blockIdx.x, gridDim.x) * 2 + bslot;
+        active = blk < a.bh * a.bw;
     }
     BlockGeo g;
-    block_geo(a, B, blk, g);
-    uint64_t best = ~0ull;
-    if (g.dxlo <= g.dxhi && g.dylo <= g.dyhi) {
-        const int nx = g.dxhi - g.dxlo + 1, ny = g.dyhi - g.dylo + 1;
-        const int nc = nx * ny, rows = 2 * g.h;
+    int nc = 0, nx = 1;
+    if (active) {
+        block_geo(a, B, blk, g);
+        if (g.dxlo <= g.dxhi && g.dylo <= g.dyhi) {
+            nx = g.dxhi - g.dxlo + 1;
+            nc = nx * (g.dyhi - g.dylo + 1);
+        }
+    }
+    if (nc > 0) {
+        const int ny = nc / nx, rows = 2 * g.h;
+        const int rlo = half ? rows / 2 : 0, hr = (half ? rows : rows / 2) - rlo;   // this wave's mosaic rows
         uint32_t* win = reinterpret_cast<uint32_t*>(lds_dyn) + wave * a.band_ty;
-        uint32_t* cblk = win + 2 * (B + 2 * a.R) * a.lds_pitch;        // 2B rows of B words
-        stage_window(a, win, 2LL * (g.y0 + g.dylo), g.x0 + g.dxlo, 2 * (g.h + ny - 1), 0, 1, lane);
+        uint32_t* cblk = win + 2 * (B + 2 * a.R) * a.lds_pitch;        // the half's rows of B words
+        stage_window(a, win, 2LL * (g.y0 + g.dylo) + rlo, g.x0 + g.dxlo, hr + 2 * (ny - 1), 0, 1, lane);
         {
-            const int64_t c0 = 2LL * g.y0 * a.cur_pitch + g.x0;
-            for (int r = 0; r < rows; ++r)
+            const int64_t c0 = (2LL * g.y0 + rlo) * a.cur_pitch + g.x0;
+            for (int r = 0; r < hr; ++r)
                 if (lane < g.w) __builtin_amdgcn_global_load_lds(a.cur + c0 + r * a.cur_pitch + lane, cblk + r * B, 4, 0, 0);
         }
         __builtin_amdgcn_s_waitcnt(0);
@@ -946,7 +959,7 @@ __global__ __launch_bounds__(256) void sad_small_kernel(SearchArgs a_in)
         while (S < 64 && 2 * S * nc <= 64) S *= 2;
         const int stride = 64 / S;
         const int slice = lane / stride, c0 = lane - slice * stride;
-        const int r0 = slice * rows / S, r1 = (slice + 1) * rows / S;
+        const int r0 = slice * hr / S, r1 = (slice + 1) * hr / S;
         for (int base = 0; base < nc; base += stride) {
             const int cand = base + c0;
             uint32_t part = 0u;
@@ -957,12 +970,17 @@ __global__ __launch_bounds__(256) void sad_small_kernel(SearchArgs a_in)
                                 : lds_rows_sad<0>(cblk, B, rl, a.lds_pitch, r0, r1, g.w);
             }
             for (int off = stride; off < 64; off <<= 1) part += __shfl_xor(part, off, 64);
-            if (cand < nc && slice == 0) {
-                const int cy = cand / nx, cx = cand - cy * nx;
-                const uint64_t key = make_key(part, g.dxlo + cx, g.dylo + cy);
-                best = key < best ? key : best;
-            }
+            if (cand < nc && slice == 0) halves[bslot][half][cand] = part;
         }
+    }
+    __syncthreads();                                     // every wave reaches it: no early return above
+    if (!active || half != 0) return;
+    uint64_t best = ~0ull;
+    for (int cand = lane; cand < nc; cand += 64) {
+        const uint32_t sad = halves[bslot][0][cand] + halves[bslot][1][cand];
+        const int cy = cand / nx, cx = cand - cy * nx;
+        const uint64_t key = make_key(sad, g.dxlo + cx, g.dylo + cy);
+        best = key < best ? key : best;
     }
     best = wave_min_u64(best);
     if (lane == 0) write_result(a, blk, best);
@@ -1351,8 +1369,8 @@ hipError_t launch_sad_search(const SearchArgs& a, const TileCfg& cfg_in, int n_w
         b.band_ty = swords;                             // words per wave slice
         const int64_t nblk = a.list ? n_wg : njobs * a.bh * a.bw;
         if (nblk <= 0) return hipSuccess;
-        if ((nblk + 3) / 4 > 0x7fffffff) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(sk, dim3((unsigned)((nblk + 3) / 4)), dim3(256), bytes, stream, b);
+        if ((nblk + 1) / 2 > 0x7fffffff) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(sk, dim3((unsigned)((nblk + 1) / 2)), dim3(256), bytes, stream, b);   // two blocks per workgroup
         return hipGetLastError();
     }
     if (a.net) return hipErrorInvalidValue;          // decoded predictors: small-radius kernel only
