@@ -58,8 +58,9 @@ def sad_ops(Hp, Wp, B, R):
     return tot
 
 
-def cpu_baseline(frames, feats, B, R, budget_s):
-    """The CPU oracle, as it stands, on whole 1080p pairs until the budget is used."""
+def cpu_baseline(frames, feats, B, R, budget_s, uhd_pair=True):
+    """The CPU oracle, as it stands, on whole 1080p pairs until the budget is used
+    (all host cores), plus sampled single-thread and 4K rates."""
     import numpy as np
 
     import oracle
@@ -81,9 +82,32 @@ def cpu_baseline(frames, feats, B, R, budget_s):
             model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
     except OSError:
         pass
-    return {"value": n / el, "unit": "frames/s", "cores": cores, "kind": "oracle", "cpu_model": model,
-            "sample": "%d consecutive 1080p pairs, full search B=%d R=%d over all blocks + float64 warp of "
-                      "[%d,%d,%d], %.1f s" % (n, B, R, *feats.shape, el)}
+    res = {"value": n / el, "unit": "frames/s", "cores": cores, "kind": "oracle", "cpu_model": model,
+           "sample": "%d consecutive 1080p pairs, full search B=%d R=%d over all blocks + float64 warp of "
+                     "[%d,%d,%d], %.1f s" % (n, B, R, *feats.shape, el)}
+    # the same oracle on one thread and on a 4K R=64 pair: every 8th block of one pair each, the
+    # SAD-op rate scaled to whole pairs (full search only)
+    H, W = frames[0].shape
+    nblk = ((H // 2 + B - 1) // B) * ((W // 2 + B - 1) // B)
+    t1 = time.perf_counter()
+    _, _, ops = oracle.full_search(frames[0], frames[1], B, R, blocks=np.arange(0, nblk, 8), nthreads=1)
+    rate1 = ops / (time.perf_counter() - t1)
+    res["single_thread"] = {"value": round(rate1 / sad_ops(H // 2, W // 2, B, R), 4), "unit": "frames/s",
+                            "cores": 1, "sad_ops_per_s": round(rate1), "sample": "every 8th block of one 1080p "
+                            "pair, full search only, scaled to whole pairs"}
+    if uhd_pair:
+        from paper_2508_05990_amd import synth
+
+        uhd = synth.uhd_sequence(4, n_frames=2).frames
+        Hu, Wu = uhd[0].shape
+        nbu = ((Hu // 2 + 15) // 16) * ((Wu // 2 + 15) // 16)
+        t1 = time.perf_counter()
+        _, _, ops = oracle.full_search(uhd[0], uhd[1], 16, 64, blocks=np.arange(0, nbu, 8), nthreads=cores)
+        rate = ops / (time.perf_counter() - t1)
+        res["uhd_r64"] = {"value": round(rate / sad_ops(Hu // 2, Wu // 2, 16, 64), 4), "unit": "frames/s",
+                          "cores": cores, "sad_ops_per_s": round(rate), "sample": "every 8th block of one 3840x2160 "
+                          "pair, full search B=16 R=64 only, scaled to whole pairs"}
+    return res
 
 
 def proposal_leg(me, ctx, frames, mvs_exh, z, outs, B, R, H, W, args):

@@ -53,7 +53,7 @@ def test_hd_feature_map(dev, oracle_mod, bf16):
 
 @pytest.mark.parametrize("bf16", [False, True])
 @pytest.mark.parametrize("s,B,C,Hf,Wf", [(4, 16, 3, 17, 23), (2, 8, 5, 31, 9), (1, 8, 2, 40, 33), (8, 64, 7, 9, 14),
-                                         (16, 32, 2, 5, 7)])
+                                         (16, 32, 2, 5, 7), (8, 8, 3, 11, 13), (4, 16, 2, 6, 2)])
 def test_ragged_shapes(dev, oracle_mod, bf16, s, B, C, Hf, Wf):
     rng = np.random.default_rng(s * 100 + C)
     z = rng.standard_normal((C, Hf, Wf)).astype(np.float32)
@@ -77,3 +77,4 @@ def test_whole_cell_mv_is_exact_shift(dev, oracle_mod):
     mv[..., 0], mv[..., 1] = -8, 12          # two cells left, three down (s = 4)
     got, ref = _check(dev, oracle_mod, z, mv, 16, 160, 256, False)
     assert np.array_equal(got, ref)
+
