@@ -37,6 +37,25 @@ def progress(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def settle(step, seconds):
+    """Run ``step`` untimed for ``seconds`` of wall time before a leg's warm-up steps.  A GPU that has
+    been idle (sequence generation, the previous leg's host work) starts at a lower clock and needs
+    about 15 ms of sustained work to reach its steady one: in a kernel trace the 1080p search took
+    154 us at the start of a leg and 138 us after 15 ms.  Returns the number of steps run."""
+    import torch
+
+    torch.cuda.synchronize()
+    t_end = time.perf_counter() + seconds
+    n = 0
+    while time.perf_counter() < t_end:
+        step()
+        n += 1
+        if n % 4 == 0:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    return n
+
+
 def sad_traffic():
     import hashlib
 
@@ -152,6 +171,7 @@ def proposal_leg(me, ctx, frames, mvs_exh, z, outs, B, R, H, W, args):
                     ev[t][1].record()
                 me.warp_features(z, mv[t], B, H, W, out=outs[t & 1], ctx=ctx)
 
+        settle(step, args.settle)
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
@@ -204,6 +224,7 @@ def pyramid_leg(me, ctx, frames, mvs_exh, z, outs, B, R, H, W, args):
                 ev[t][1].record()
             me.warp_features(z, mv[t], B, H, W, out=outs[t & 1], ctx=ctx)
 
+    settle(step, args.settle)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -387,6 +408,7 @@ def fused_leg(me, ctx, frames, z, mvs, sads, outs, B, R, H, W, args):
             if t == ts:
                 ev[1].record()
 
+    settle(step, args.settle)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -657,25 +679,28 @@ def bf16_step_leg(me, ctx, frames, mvs, sads, B, R, H, W, args):
     params = me.make_params(B, R)
     npairs = len(frames) - 1
 
-    def step(ev=None, ts=-1):
+    # the headline step's order: the 15 searches, then the 15 warps between two events
+    def step(ev=None):
         for t in range(npairs):
             me.estimate(frames[t], frames[t + 1], mv=mvs[t], sad=sads[t], params=params, ctx=ctx)
-            if t == ts:
-                ev[0].record()
+        if ev is not None:
+            ev[0].record()
+        for t in range(npairs):
             me.warp_features(z, mvs[t], B, H, W, out=outs[t & 1], ctx=ctx)
-            if t == ts:
-                ev[1].record()
+        if ev is not None:
+            ev[1].record()
 
+    settle(step, args.settle)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step(evs[k], k % npairs)
+        step(evs[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    us = float(np.mean([e[0].elapsed_time(e[1]) for e in evs])) * 1e3
+    us = float(np.mean([e[0].elapsed_time(e[1]) for e in evs])) * 1e3 / npairs
     wb = 2 * z.numel() * z.element_size()
     return {"value": round(npairs * args.steps / wall, 2), "unit": "frames/s", "warp_dtype": "bf16",
             "warp_us_per_pair": round(us, 3), "warp_hbm_frac": round(wb / (us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4),
@@ -687,6 +712,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--settle", type=float, default=0.2,
+                    help="seconds of untimed steps before each leg's warm-up, to reach the sustained clock")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline budget (0 = skip)")
     ap.add_argument("--warp-dtype", choices=["f32", "bf16"], default="f32")
     ap.add_argument("--no-proposal", action="store_true", help="skip the learned-proposal measurement")
@@ -742,19 +769,22 @@ def main():
     ctx = me.Context(0)
     params = me.make_params(B, R)
 
-    # Kernel durations come from events recorded around ONE pair per timed step, the pair index rotating
-    # with the step: markers around every launch stall the stream between kernels (about 10 us per pair).
-    def step(ev=None, ts=-1):
+    # A step runs the 15 searches, then the 15 warps (each warp needs only its own pair's vectors).  Kernel
+    # durations come from three events per timed step around the two runs of back-to-back launches, so the
+    # averages include the gaps between launches and no marker sits between two kernels.
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record()
         for t in range(npairs):
-            if t == ts:
-                ev[0].record()
             me.estimate(frames[t], frames[t + 1], mv=mvs[t], sad=sads[t], params=params, ctx=ctx)
-            if t == ts:
-                ev[1].record()
+        if ev is not None:
+            ev[1].record()
+        for t in range(npairs):
             me.warp_features(z, mvs[t], B, H, W, out=outs[t & 1], ctx=ctx)
-            if t == ts:
-                ev[2].record()
+        if ev is not None:
+            ev[2].record()
 
+    settle(step, args.settle)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -763,7 +793,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step(evs[k], k % npairs)
+        step(evs[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
@@ -777,8 +807,8 @@ def main():
         torch.cuda.synchronize()
         rep_ms.append((time.perf_counter() - t1) * 1e3 / args.steps)
 
-    me_ms = [e[0].elapsed_time(e[1]) for e in evs]
-    warp_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    me_ms = [e[0].elapsed_time(e[1]) / npairs for e in evs]
+    warp_ms = [e[1].elapsed_time(e[2]) / npairs for e in evs]
     me_avg = float(np.mean(me_ms))
     warp_avg = float(np.mean(warp_ms))
     ops = sad_ops(Hp, Wp, B, R)
@@ -793,6 +823,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "settle_s": args.settle,
         "ms_per_step": round(wall * 1e3 / args.steps, 4),
         "higher_is_better": True,
         "scaling": "weak",
