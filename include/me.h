@@ -482,6 +482,19 @@ me_status me_prnet_forward(me_prnet net, const me_frame* cur, int32_t n, int64_t
                            void* z_out, int32_t dtype, void* stream);
 
 /*
+ * me_prnet_forward_acts -- me_prnet_forward that also copies out the stage
+ * outputs of the inference pass (paper Sec. 3.3: encoder, projection,
+ * inverted residual blocks), so that its fused kernels can be checked stage
+ * by stage: enc = device [n][Hf][Wf][c_enc] bfloat16 (the encoder output),
+ * hid = device [n_blocks + 1][n][Hf][Wf][c_hid] bfloat16 (the projection
+ * output, then each block's output).  Either may be NULL; the other
+ * arguments, errors and ordering are those of me_prnet_forward.
+ */
+me_status me_prnet_forward_acts(me_prnet net, const me_frame* cur, int32_t n, int64_t frame_stride,
+                                const void* z_pred, void* z_out, int32_t dtype, uint16_t* enc, uint16_t* hid,
+                                void* stream);
+
+/*
  * me_prnet_train_step -- forward, weighted BerHu loss against z_target, backward
  * (paper Sec. 3.3) and, when update != 0, one AdamW step (beta 0.9, 0.999,
  * eps 1e-8, weight decay 0.01, decoupled; learning rate lr).  z_pred, z_target:

@@ -575,6 +575,22 @@ me_status me_prnet_forward(me_prnet net, const me_frame* cur, int32_t n, int64_t
     return e == hipSuccess ? ME_OK : hip_fail(e, "me_prnet_forward");
 }
 
+me_status me_prnet_forward_acts(me_prnet net, const me_frame* cur, int32_t n, int64_t frame_stride,
+                                const void* z_pred, void* z_out, int32_t dtype, uint16_t* enc, uint16_t* hid,
+                                void* stream)
+{
+    me_status s = me_prnet_forward(net, cur, n, frame_stride, z_pred, z_out, dtype, stream);
+    if (s != ME_OK) return s;
+    hipStream_t st = as_stream(stream);
+    const size_t P2 = (size_t)net->n * net->Hf * net->Wf;
+    hipError_t e = hipSuccess;
+    if (enc) e = hipMemcpyAsync(enc, net->e4, P2 * net->cfg.c_enc * 2, hipMemcpyDeviceToDevice, st);
+    for (int k = 0; hid && k <= net->cfg.n_blocks && e == hipSuccess; ++k)
+        e = hipMemcpyAsync(hid + (size_t)k * P2 * net->cfg.c_hid, net->h[k], P2 * net->cfg.c_hid * 2,
+                           hipMemcpyDeviceToDevice, st);
+    return e == hipSuccess ? ME_OK : hip_fail(e, "me_prnet_forward_acts: copies");
+}
+
 me_status me_prnet_train_step(me_prnet net, const me_frame* cur, int32_t n, int64_t frame_stride, const float* z_pred,
                               const float* z_target, float tau, float lr, int32_t update, float* grads, float* loss,
                               void* stream)

@@ -116,6 +116,8 @@ _me_prnet_destroy = _sig("me_prnet_destroy", [_P])
 _me_prnet_set_params = _sig("me_prnet_set_params", [_P, _P, _I64])
 _me_prnet_get_params = _sig("me_prnet_get_params", [_P, _P, _I64])
 _me_prnet_forward = _sig("me_prnet_forward", [_P, ctypes.POINTER(MeFrame), _I32, _I64, _P, _P, _I32, _P])
+_me_prnet_forward_acts = _sig("me_prnet_forward_acts",
+                              [_P, ctypes.POINTER(MeFrame), _I32, _I64, _P, _P, _I32, _P, _P, _P])
 _me_prnet_train_step = _sig("me_prnet_train_step", [_P, ctypes.POINTER(MeFrame), _I32, _I64, _P, _P, _F, _F, _I32,
                                                     _P, _P, _P])
 _me_prnet_dw_forward = _sig("me_prnet_dw_forward", [_P, _P, _P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P])
@@ -627,6 +629,20 @@ class Prnet:
         _check(_me_prnet_forward(self.handle, ctypes.byref(fr), c.shape[0], c.stride(0), z.data_ptr(), out.data_ptr(),
                                  dt, _stream_handle(stream)))
         return out if z_pred.dim() == 4 else out[0]
+
+    def forward_acts(self, cur: torch.Tensor, z_pred: torch.Tensor, stream=None):
+        """forward() on [n, H, W] mosaics and [n, c_feat, Hf, Wf] features that also returns the stage
+        outputs: (z_out, enc [n, Hf, Wf, c_enc] bfloat16, hid [n_blocks + 1, n, Hf, Wf, c_hid] bfloat16)."""
+        n, Hf, Wf = z_pred.shape[0], z_pred.shape[2], z_pred.shape[3]
+        out = torch.empty_like(z_pred)
+        enc = torch.empty((n, Hf, Wf, self.cfg.c_enc), dtype=torch.bfloat16, device=z_pred.device)
+        hid = torch.empty((self.cfg.n_blocks + 1, n, Hf, Wf, self.cfg.c_hid), dtype=torch.bfloat16,
+                          device=z_pred.device)
+        dt = ME_BF16 if z_pred.dtype == torch.bfloat16 else ME_F32
+        fr = frame_of(cur[0])
+        _check(_me_prnet_forward_acts(self.handle, ctypes.byref(fr), n, cur.stride(0), z_pred.data_ptr(),
+                                      out.data_ptr(), dt, enc.data_ptr(), hid.data_ptr(), _stream_handle(stream)))
+        return out, enc, hid
 
     def train_step(self, cur, z_pred, z_target, tau=-1.0, lr=1e-3, update=True, grads=None, loss=None, stream=None):
         c = cur if cur.dim() == 3 else cur[None]

@@ -9,7 +9,8 @@ Tolerances.  A layer output is a float32 sum rounded to bfloat16, so it lies
 within half a bfloat16 step (2^-8 relative) plus the float32 summation error
 (1e-6 of the sum of |terms|) of the exact float64 value.
 Whole-network results compound one rounding per stored activation; they are
-compared by relative norm."""
+compared by relative norm here, and stage by stage, element by element, in
+test_gpu_prnet_stages.py."""
 import numpy as np
 import pytest
 
