@@ -678,7 +678,11 @@ __global__ __launch_bounds__(256) void reduce_rows_kernel(const float* __restric
 // the layer-by-layer path (u, v and h_out are bfloat16).  About 44 KB of LDS
 // per workgroup at 64 hidden channels.
 constexpr int kIrT = 8, kIrHW = kIrT + 2, kIrHalo = kIrHW * kIrHW, kIrRows = 112;
-constexpr int kIrChunk = 64, kIrLd = kIrChunk + 8;
+// Row strides (bfloat16 elements) of the staged h (CH + kIrPadH) and of the u
+// and v chunks (kIrLd): multiples of 4 (8-byte lane reads), padded so that the
+// sixteen rows of an MFMA operand read spread over the LDS banks.
+constexpr int kIrPadH = 4, kIrPadU = 4;
+constexpr int kIrChunk = 64, kIrLd = kIrChunk + kIrPadU;
 // Eight waves: wave w takes the 16-channel row tile w % 4 of each product and
 // the pixel column tiles of half w / 4 (expansion: halo column tiles 0-3 or
 // 4-6; compression: output column tiles 0-1 or 2-3).
@@ -689,10 +693,10 @@ __global__ __launch_bounds__(kIrThreads) void ir_block_kernel(IrArgs a)
 {
     extern __shared__ __align__(16) uint16_t lds[];
     const int X = a.x;
-    constexpr int ldh = CH + 8;
-    uint16_t* hl = lds;                                   // [112][CH + 8]   h over tile + halo
-    uint16_t* ul = hl + kIrRows * ldh;                     // [112][72]       u, one chunk
-    uint16_t* vl = ul + kIrRows * kIrLd;                   // [64][72]        v, one chunk
+    constexpr int ldh = CH + kIrPadH;
+    uint16_t* hl = lds;                                   // [112][ldh]      h over tile + halo
+    uint16_t* ul = hl + kIrRows * ldh;                     // [112][kIrLd]    u, one chunk
+    uint16_t* vl = ul + kIrRows * kIrLd;                   // [64][kIrLd]     v, one chunk
     float* wl = reinterpret_cast<float*>(vl + kIrT * kIrT * kIrLd);   // [X][10] depthwise weights + bias, [X] expansion bias
     const int tiles_x = (a.Wf + kIrT - 1) / kIrT, tiles_y = (a.Hf + kIrT - 1) / kIrT;
     const int img = blockIdx.x / (tiles_x * tiles_y), tr = blockIdx.x - img * tiles_x * tiles_y;
@@ -1340,7 +1344,7 @@ hipError_t launch_planes(const uint16_t* m, int64_t pitch, int64_t img_stride, i
 
 size_t ir_lds_bytes(int ch, int x)
 {
-    return (size_t)(kIrRows * (ch + 8) + kIrRows * kIrLd + kIrT * kIrT * kIrLd) * sizeof(uint16_t) +
+    return (size_t)(kIrRows * (ch + kIrPadH) + kIrRows * kIrLd + kIrT * kIrT * kIrLd) * sizeof(uint16_t) +
            (size_t)x * 11 * sizeof(float);
 }
 
