@@ -122,6 +122,25 @@ __device__ __forceinline__ void stage_window(const SearchArgs& a, uint32_t* lds,
     }
 }
 
+// Rows [grow0, grow0 + nrows) x words [gcol0, gcol0 + width) of src (rows
+// src_pitch words apart) into LDS as contiguous rows of `width` words: 64
+// words per wave instruction whatever the row width (a narrow window takes a
+// few instructions instead of one per row).  Rows past rmax and columns past
+// cmax read the nearest in-frame word (only discarded candidates meet them).
+// The caller waits (vmcnt).
+__device__ __forceinline__ void stage_packed(const uint32_t* src, int64_t src_pitch, int64_t grow0, int gcol0, int width,
+                                             int nrows, int64_t rmax, int cmax, uint32_t* lds, int lane)
+{
+    const int total = nrows * width;
+    for (int f0 = 0; f0 < total; f0 += 64) {
+        const int f = f0 + lane;
+        const int r = f / width, c = f - r * width;
+        const int64_t gr = min(grow0 + r, rmax);
+        const int gc = min(gcol0 + c, cmax);
+        if (f < total) __builtin_amdgcn_global_load_lds(src + gr * src_pitch + gc, lds + f0, 4, 0, 0);
+    }
+}
+
 __device__ __forceinline__ void write_result(const SearchArgs& a, int blk, uint64_t b)
 {
     if (b == ~0ull) {
@@ -948,12 +967,9 @@ __global__ __launch_bounds__(256) void sad_small_kernel(SearchArgs a_in)
         const int rlo = half ? rows / 2 : 0, hr = (half ? rows : rows / 2) - rlo;   // this wave's mosaic rows
         uint32_t* win = reinterpret_cast<uint32_t*>(lds_dyn) + wave * a.band_ty;
         uint32_t* cblk = win + 2 * (B + 2 * a.R) * a.lds_pitch;        // the half's rows of B words
-        stage_window(a, win, 2LL * (g.y0 + g.dylo) + rlo, g.x0 + g.dxlo, hr + 2 * (ny - 1), 0, 1, lane);
-        {
-            const int64_t c0 = (2LL * g.y0 + rlo) * a.cur_pitch + g.x0;
-            for (int r = 0; r < hr; ++r)
-                if (lane < g.w) __builtin_amdgcn_global_load_lds(a.cur + c0 + r * a.cur_pitch + lane, cblk + r * B, 4, 0, 0);
-        }
+        stage_packed(a.ref, a.ref_pitch, 2LL * (g.y0 + g.dylo) + rlo, g.x0 + g.dxlo, a.lds_pitch, hr + 2 * (ny - 1),
+                     2LL * a.Hp - 1, a.Wp - 1, win, lane);
+        stage_packed(a.cur, a.cur_pitch, 2LL * g.y0 + rlo, g.x0, B, hr, 2LL * a.Hp - 1, a.Wp - 1, cblk, lane);
         __builtin_amdgcn_s_waitcnt(0);
         int S = 1;
         while (S < 64 && 2 * S * nc <= 64) S *= 2;
