@@ -3,7 +3,9 @@ bit for bit: full search over random frame sizes, block sizes and radii
 (textured shifted pairs, low-entropy frames full of ties, full 16-bit noise),
 and the learned-proposal refine + fallback over random network outputs,
 thresholds, refine radii (the small-radius kernel and the predictor path)
-and SAD medians.  Fixed seeds and case counts: the same cases every run."""
+and SAD medians; and batched submissions of random job mixes (frame sizes,
+block sizes, radii) through the persistent per-block-size queue.  Fixed seeds
+and case counts: the same cases every run."""
 import numpy as np
 import pytest
 
@@ -89,3 +91,32 @@ def test_refine_sweep(dev, ctx, oracle_mod, seed):
         assert np.array_equal(fb.cpu().numpy(), fb_o), what
         assert np.array_equal(sad.cpu().numpy(), sad_o), what
         assert np.array_equal(mv.cpu().numpy(), mv_o), what
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_batch_sweep(dev, ctx, oracle_mod, seed):
+    """Two submissions per seed of 3-10 random jobs each (partial blocks on
+    both edges, radii with and without a shared two-block window); every
+    job's vectors and SADs against the oracle's full search."""
+    import torch
+
+    rng = np.random.default_rng(9200 + seed)
+    for sub in range(2):
+        jobs = []
+        for _ in range(int(rng.integers(3, 11))):
+            B = int(rng.choice([8, 16, 32, 64]))
+            R = int(rng.choice([3, 5, 8, 12, 16, 17, 24, 32, 33, 40]))
+            H, W = 2 * int(rng.integers(8, 200)), 2 * int(rng.integers(8, 260))
+            f0, f1 = _frames(rng, H, W, R, int(rng.integers(0, 3)))
+            bh, bw = dev.block_grid(H, W, B)
+            jobs.append(dict(f0=f0, f1=f1, B=B, R=R, t0=torch.from_numpy(f0).cuda(), t1=torch.from_numpy(f1).cuda(),
+                             mv=torch.full((bh, bw, 2), 77, dtype=torch.int16, device="cuda"),
+                             sad=torch.full((bh, bw), -7, dtype=torch.int32, device="cuda")))
+        print("batch sweep", seed, sub, [(j["f0"].shape, j["B"], j["R"]) for j in jobs], flush=True)
+        dev.batch_submit(ctx, [(j["t0"], j["t1"], j["B"], j["R"], j["mv"], j["sad"]) for j in jobs])
+        torch.cuda.synchronize()
+        for k, j in enumerate(jobs):
+            mv_o, sad_o, _ = oracle_mod.full_search(j["f0"], j["f1"], j["B"], j["R"])
+            what = (seed, sub, k, j["f0"].shape, j["B"], j["R"])
+            assert np.array_equal(j["sad"].cpu().numpy(), sad_o), what
+            assert np.array_equal(j["mv"].cpu().numpy(), mv_o), what
